@@ -1,0 +1,177 @@
+"""p-multigrid V-cycle on the Chebyshev order (Alg. 1), as a plain composition of dense steps.
+
+Oracle (test infrastructure only).
+
+- Coarsening (Sec. 4.1): the rule doubles, level by level towards the fine grid, whichever of the
+  two orders is smaller (the printed conditions "= and <" are read as "<="). Going coarse it
+  therefore halves the smaller order. Every grid used here has Nx >= 2M, so only the Chebyshev
+  order is coarsened: M_l = M / 2^l down to M_L = 2, with Nx and the x-metrics unchanged.
+- Coarse operators are the same discrete operator re-discretised at order M_l.
+- Transfers (Sec. 4.2): restriction takes Chebyshev coefficients, drops the modes above the coarse
+  order and evaluates at the coarse nodes; prolongation is the zero-padded expansion evaluated at
+  the fine nodes (polynomial interpolation). The residual's boundary rows are injected: the
+  coarse surface and bed rows take the fine surface and bed rows, which sit at the same sigma.
+- Smoother (Sec. 4.3): the paper smooths with Gauss-Seidel over column blocks A_rr (one block per
+  x column, Nz x Nz). The oracle keeps that block: the x-diagonal block of A at column i. Its
+  relaxation is parallel (block Jacobi, damping omega_c), and it is paired with a second line
+  relaxation along x: the exact inverse of the x-averaged flat operator, mode by mode (damping
+  omega_m). One "pair" is a column step followed by a mode step, each from the current residual.
+- Coarsest level (Alg. 1, p = 1): the paper uses a direct solver. Here the coarsest level still
+  couples all Nx columns densely, so the oracle runs ``coarse_pairs`` smoothing pairs from a zero
+  guess there (a fixed linear map); ``coarse='exact'`` uses a dense LU instead, for comparison.
+- V-cycle: zero initial guess; nu1 pre-smoothing pairs, residual, restriction, recursive call whose
+  result is the coarse correction (the listing leaves that assignment implicit), prolongation,
+  correction, nu2 post-smoothing pairs.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import operator as op
+from . import spectral as sp
+
+
+@dataclass
+class PmgOptions:
+    nu1: int = 1
+    nu2: int = 1
+    omega_c: float = 1.0
+    omega_m: float = 1.0
+    coarse_pairs: int = 4
+    coarse: str = "smooth"        # "smooth" (fixed pairs) or "exact" (dense LU)
+
+
+def level_orders(M):
+    """M, M/2, ..., 2 (M must be a power of two >= 2)."""
+    out = [M]
+    while out[-1] > 2:
+        out.append(out[-1] // 2)
+    return out
+
+
+def restriction_matrix(Mf):
+    """(Mc+1) x (Mf+1): coefficients, truncate to Mc = Mf/2, evaluate at coarse nodes; inject rows 0, M."""
+    Mc = Mf // 2
+    C = sp.cheb_forward_matrix(Mf)[: Mc + 1]
+    E = sp.cheb_eval_matrix(Mc, sp.cgl_xi(Mc))
+    R = E @ C
+    R[0] = 0.0
+    R[0, 0] = 1.0
+    R[Mc] = 0.0
+    R[Mc, Mf] = 1.0
+    return R
+
+
+def prolongation_matrix(Mf):
+    """(Mf+1) x (Mc+1): interpolate the coarse-degree polynomial at the fine nodes."""
+    Mc = Mf // 2
+    C = sp.cheb_forward_matrix(Mc)
+    E = sp.cheb_eval_matrix(Mc, sp.cgl_xi(Mf))
+    return E @ C
+
+
+def dxx_diagonal(nx, L):
+    """Diagonal entry of D_x D_x: -(1/nx) sum_k kappa_k^2 with the Nyquist mode zeroed."""
+    return -float(np.sum(sp.wavenumbers(nx, L) ** 2)) / nx
+
+
+def column_blocks(nx, M, g_old, g_new):
+    """B_i = x-diagonal block of A at column i (formula), array [nx, Nz, Nz].
+
+    Interior rows: diag(D_xx) I + diag(sx_n) D_s diag(sx_o) D_s + D_s^2 / (d_n d_o); row 0 = e_0;
+    row M = -(h_x sx_o[M] + 1/d_o) (D_s)_M. (D_x has a zero diagonal, so the mixed x-sigma terms
+    contribute nothing to the block.)
+    """
+    nz = M + 1
+    Ds = sp.dsig_matrix(M)
+    sig = sp.cgl_sigma(M)
+    sxo = g_old.sigma_x(sig)
+    sxn = g_new.sigma_x(sig)
+    cxx = dxx_diagonal(nx, g_old.L)
+    out = np.empty((nx, nz, nz))
+    for i in range(nx):
+        B = cxx * np.eye(nz) + np.diag(sxn[:, i]) @ Ds @ np.diag(sxo[:, i]) @ Ds \
+            + g_new.inv_d[i] * g_old.inv_d[i] * (Ds @ Ds)
+        B[0] = 0.0
+        B[0, 0] = 1.0
+        B[M] = -(g_old.hx[i] * sxo[M, i] + g_old.inv_d[i]) * Ds[M]
+        out[i] = B
+    return out
+
+
+def column_blocks_from_dense(A, nx, M):
+    """The same blocks read off an assembled matrix (the definition); used by the pins."""
+    nz = M + 1
+    out = np.empty((nx, nz, nz))
+    for i in range(nx):
+        idx = np.arange(nz) * nx + i
+        out[i] = A[np.ix_(idx, idx)]
+    return out
+
+
+class Level:
+    def __init__(self, nx, M, g_old, g_new):
+        self.nx, self.M = nx, M
+        self.g_old, self.g_new = g_old, g_new
+        self.col = column_blocks(nx, M, g_old, g_new)
+        cbar, ebar = op.flat_coefficients(g_old, g_new)
+        self.mode = op.flat_mode_blocks(nx, M, g_old.L, cbar, ebar)
+        self._coarse_lu = None
+
+    def apply(self, x):
+        return op.apply(x, self.g_old, self.g_new)
+
+    def column_step(self, x, f, omega):
+        r = f - self.apply(x)
+        corr = np.empty_like(r)
+        for i in range(self.nx):
+            corr[:, i] = np.linalg.solve(self.col[i], r[:, i])
+        return x + omega * corr
+
+    def mode_step(self, x, f, omega):
+        r = f - self.apply(x)
+        return x + omega * op.flat_mode_solve(r, self.mode)
+
+    def pair(self, x, f, o):
+        x = self.column_step(x, f, o.omega_c)
+        return self.mode_step(x, f, o.omega_m)
+
+    def exact(self, f):
+        if self._coarse_lu is None:
+            A = op.assemble(self.nx, self.M, self.g_old, self.g_new)
+            self._coarse_lu = sla.lu_factor(A)
+        return sla.lu_solve(self._coarse_lu, f.ravel()).reshape(f.shape)
+
+
+class Hierarchy:
+    """Levels M_l = M/2^l (fine to coarse) with transfers; ``vcycle`` is Alg. 1 from a zero guess."""
+
+    def __init__(self, nx, M, g_old, g_new, opts=None):
+        self.opts = opts or PmgOptions()
+        self.orders = level_orders(M)
+        self.levels = [Level(nx, m, g_old, g_new) for m in self.orders]
+        self.R = [restriction_matrix(m) for m in self.orders[:-1]]
+        self.P = [prolongation_matrix(m) for m in self.orders[:-1]]
+
+    def vcycle(self, f, l=0):
+        o = self.opts
+        lev = self.levels[l]
+        x = np.zeros_like(f)
+        if l == len(self.levels) - 1:
+            if o.coarse == "exact":
+                return lev.exact(f)
+            for _ in range(o.coarse_pairs):
+                x = lev.pair(x, f, o)
+            return x
+        for _ in range(o.nu1):
+            x = lev.pair(x, f, o)
+        r = f - lev.apply(x)
+        ec = self.vcycle(self.R[l] @ r, l + 1)
+        x = x + self.P[l] @ ec
+        for _ in range(o.nu2):
+            x = lev.pair(x, f, o)
+        return x
+
+    def __call__(self, f):
+        return self.vcycle(np.asarray(f))

@@ -1,0 +1,241 @@
+"""Seeded synthetic workloads for the pressure Poisson solve and the RK time stepping.
+
+This module generates inputs only: bathymetry h(x), surface elevation eta(x), right-hand sides and
+initial fields, all from closed-form expressions evaluated at the grid nodes. It holds none of the
+method's arithmetic (no derivative operators, no metrics, no solves), so the GPU path and the CPU
+checker can both draw their inputs from it.
+
+Fields are float64 arrays laid out [Nz][Nx]: row j sits at sigma_j = (1 + cos(j pi / M)) / 2
+(row 0 = free surface, row M = bed), column i at x_i = i L / Nx.
+
+The paper's own workloads (stream-function waves, the Beji-Battjes flume record) are not
+available; the recipes below stand in for them with the same shapes, depths, wave steepnesses and
+bathymetry types.
+"""
+import math
+
+import numpy as np
+
+G = 9.81
+RHO = 1000.0
+
+
+def nodes(nx, nz, L):
+    """x_i and sigma_j of the grid on which every input below is sampled."""
+    M = nz - 1
+    x = np.arange(nx, dtype=np.float64) * (L / nx)
+    sigma = 0.5 * (1.0 + np.cos(np.pi * np.arange(nz) / M))
+    return x, sigma
+
+
+def _phi(u):
+    return np.exp(-0.5 * u * u) / math.sqrt(2.0 * math.pi)
+
+
+def _Phi(u):
+    from scipy.special import ndtr
+    return ndtr(u)
+
+
+def rest_rhs(h, hx, eta_x, eta_xx, nz):
+    """Right-hand side of the first RK stage started from rest, from closed-form derivatives.
+
+    From rest (u = w = K = 0) the provisional velocity is u* = -beta dt g eta_x, uniform in sigma,
+    w* = 0, so the scaled divergence is -rho g eta_xx in the interior, 0 on the surface row and the
+    bed-normal flux rho g h_x eta_x on the bed row.
+    """
+    nx = h.shape[0]
+    b = np.empty((nz, nx))
+    b[:] = -RHO * G * eta_xx[None, :]
+    b[0] = 0.0
+    b[nz - 1] = RHO * G * hx * eta_x
+    return b
+
+
+# ----------------------------------------------------------------------------- single problems
+
+def manufactured(nx=32, nz=9, amp=0.05):
+    """Flat bed h = 1, eta = amp cos x on L = 2 pi; exact p = cos x cosh(z + h) / cosh h.
+
+    p is harmonic in (x, z) and has zero normal derivative on the flat bed, so the discrete problem
+    has b = p on the surface row and 0 elsewhere.
+    """
+    L = 2.0 * math.pi
+    x, sigma = nodes(nx, nz, L)
+    h = np.ones(nx)
+    eta = amp * np.cos(x)
+    d = h + eta
+    exact = np.cos(x)[None, :] * np.cosh(sigma[:, None] * d[None, :]) / math.cosh(1.0)
+    b = np.zeros((nz, nx))
+    b[0] = exact[0]
+    return dict(name="manufactured", nx=nx, nz=nz, L=L, h=h, eta_old=eta, eta_new=eta.copy(),
+                b=b, exact=exact)
+
+
+def manufactured_sloped(nx=32, nz=9, amp=0.05, bed=0.15, kwave=1.0):
+    """Sloped bed and wavy surface with a harmonic exact solution p = cos(k x) cosh(k (z + 1)).
+
+    h = 1 - bed sin x, eta = amp cos x, L = 2 pi. Surface row: p at z = eta; interior rows: 0;
+    bed row: the outward normal flux -(h_x p_x + p_z) at z = -h.
+    """
+    L = 2.0 * math.pi
+    x, sigma = nodes(nx, nz, L)
+    k = kwave
+    h = 1.0 - bed * np.sin(x)
+    hx = -bed * np.cos(x)
+    eta = amp * np.cos(x)
+    d = h + eta
+    z = sigma[:, None] * d[None, :] - h[None, :]
+    exact = np.cos(k * x)[None, :] * np.cosh(k * (z + 1.0))
+    zb = -h
+    px = -k * np.sin(k * x) * np.cosh(k * (zb + 1.0))
+    pz = k * np.cos(k * x) * np.sinh(k * (zb + 1.0))
+    b = np.zeros((nz, nx))
+    b[0] = exact[0]
+    b[nz - 1] = -(hx * px + pz)
+    return dict(name="manufactured_sloped", nx=nx, nz=nz, L=L, h=h, eta_old=eta,
+                eta_new=eta.copy(), b=b, exact=exact)
+
+
+def airy_pressure(nx=16, nz=17, depth=1.0, amp=1e-3, mode=2):
+    """Linear (Airy) pressure problem on a flat geometry (surface held at z = 0).
+
+    The right-hand side comes from a surface eta = amp cos(k x) through the from-rest stage:
+    b = -rho g eta_xx inside, 0 on both boundary rows; the exact dynamic pressure is
+    rho g amp cos(k x) [cosh(k (z + h)) / cosh(k h) - 1].
+    """
+    L = 2.0 * math.pi
+    x, sigma = nodes(nx, nz, L)
+    k = float(mode)
+    h = np.full(nx, depth)
+    eta_geom = np.zeros(nx)
+    eta = amp * np.cos(k * x)
+    b = rest_rhs(h, np.zeros(nx), -amp * k * np.sin(k * x), -amp * k * k * np.cos(k * x), nz)
+    z = sigma[:, None] * depth - depth
+    exact = RHO * G * amp * np.cos(k * x)[None, :] * (np.cosh(k * (z + depth)) / math.cosh(k * depth) - 1.0)
+    return dict(name="airy_pressure", nx=nx, nz=nz, L=L, h=h, eta_old=eta_geom,
+                eta_new=eta_geom.copy(), b=b, exact=exact, eta_wave=eta)
+
+
+def bar(seed=0, nx=1024, nz=33):
+    """Trapezoidal submerged bar, first RK stage from rest (single geometry).
+
+    Depth 0.4; from x0 = L/4 a 1:20 up-slope to 0.1 over 6 m, a 2 m crest, a 1:10 down-slope over
+    3 m, then flat. The corners are mollified with a Gaussian of width 0.1 m in closed form
+    (h = h0 + sum_i dm_i s G((x - x_i)/s), G(u) = u Phi(u) + phi(u)), which keeps h smooth and
+    periodic. The seed draws kh in [0.5, 2] (w.r.t. h0), L = lambda ceil(30/lambda), a phase, and a
+    band-limited noise field (modes up to nx/4) of 1 % of the amplitude; H = 0.05 h0.
+    """
+    rng = np.random.default_rng(seed)
+    h0, sg = 0.4, 0.1
+    kh = rng.uniform(0.5, 2.0)
+    k = kh / h0
+    lam = 2.0 * math.pi / k
+    L = lam * math.ceil(30.0 / lam)
+    ph = rng.uniform(0.0, 2.0 * math.pi)
+    H = 0.05 * h0
+    x, _ = nodes(nx, nz, L)
+    x0 = L / 4.0
+    br = np.array([x0, x0 + 6.0, x0 + 8.0, x0 + 11.0])
+    dm = np.array([-0.05, 0.05, 0.1, -0.1])
+    u = (x[None, :] - br[:, None]) / sg
+    h = h0 + np.sum(dm[:, None] * sg * (u * _Phi(u) + _phi(u)), axis=0)
+    hx = np.sum(dm[:, None] * _Phi(u), axis=0)
+    eta = (H / 2.0) * np.cos(k * x + ph)
+    eta_x = -(H / 2.0) * k * np.sin(k * x + ph)
+    eta_xx = -(H / 2.0) * k * k * np.cos(k * x + ph)
+    nmodes = nx // 4
+    m = np.arange(1, nmodes + 1)
+    km = 2.0 * math.pi * m / L
+    std = 0.01 * H / 2.0
+    ca = rng.standard_normal(nmodes) * std / math.sqrt(nmodes)
+    cb = rng.standard_normal(nmodes) * std / math.sqrt(nmodes)
+    arg = np.outer(km, x)
+    eta = eta + ca @ np.cos(arg) + cb @ np.sin(arg)
+    eta_x = eta_x + (-ca * km) @ np.sin(arg) + (cb * km) @ np.cos(arg)
+    eta_xx = eta_xx - (ca * km * km) @ np.cos(arg) - (cb * km * km) @ np.sin(arg)
+    b = rest_rhs(h, hx, eta_x, eta_xx, nz)
+    return dict(name=f"bar_s{seed}", nx=nx, nz=nz, L=L, h=h, eta_old=eta, eta_new=eta.copy(), b=b,
+                kh=kh)
+
+
+def tank(rng, nx, nz):
+    """One random tank of the batched workload (first stage from rest, single geometry)."""
+    hbar = rng.uniform(0.5, 2.0)
+    L = 8.0 * math.pi * hbar
+    x, _ = nodes(nx, nz, L)
+    K = 2.0 * math.pi / L
+    if rng.uniform() < 0.5:
+        h = np.full(nx, hbar)
+        hx = np.zeros(nx)
+    else:
+        Ah = rng.uniform(0.5, 1.0) * min(0.1 * L / (2.0 * math.pi), hbar - 0.5, 2.0 - hbar)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        h = hbar + Ah * np.cos(K * x + ph)
+        hx = -Ah * K * np.sin(K * x + ph)
+    m = int(rng.integers(2, 9))
+    a = rng.uniform(0.01, 0.08) * hbar
+    phe = rng.uniform(0.0, 2.0 * math.pi)
+    km = m * K
+    eta = a * np.cos(km * x + phe)
+    eta_x = -a * km * np.sin(km * x + phe)
+    eta_xx = -a * km * km * np.cos(km * x + phe)
+    b = rest_rhs(h, hx, eta_x, eta_xx, nz)
+    return dict(nx=nx, nz=nz, L=L, h=h, eta_old=eta, eta_new=eta.copy(), b=b)
+
+
+def batch(seed=0, ntanks=512, nx_choices=(64, 128, 256, 512), nz_choices=(9, 17, 33)):
+    """Many independent tanks of uneven (Nx, Nz): depth in [0.5, 2], L = 8 pi hbar, flat or cosine
+    beds (slope <= 1:10), surface amplitude in [0.01, 0.08] hbar with kh = m/4 in [0.5, 2]."""
+    rng = np.random.default_rng(seed)
+    tanks = []
+    for _ in range(ntanks):
+        nx = int(rng.choice(nx_choices))
+        nz = int(rng.choice(nz_choices))
+        tanks.append(tank(rng, nx, nz))
+    return tanks
+
+
+# ----------------------------------------------------------------------------- time stepping
+
+def stokes_wave(nx=256, nz=17, depth=1.0, k=1.0, steep=0.05, cfl=0.5):
+    """Second-order Stokes wave initial state on a flat bed (periodic, one wavelength per L).
+
+    eta = (H/2) cos(kx) + (k H^2/16) cosh(kh)(2 + cosh 2kh)/sinh^3(kh) cos(2kx);
+    phi = (g H / 2w) cosh(k(z+h))/cosh(kh) sin(kx) + (3 H^2 w / 32) cosh(2k(z+h))/sinh^4(kh) sin(2kx),
+    u = phi_x, w = phi_z at the nodes z_ij = sigma_j d_i - h; w^2 = g k tanh(kh), H = steep * L,
+    dt = cfl * dx / c with c = w / k.
+    """
+    L = 2.0 * math.pi / k
+    H = steep * L
+    x, sigma = nodes(nx, nz, L)
+    kh = k * depth
+    om = math.sqrt(G * k * math.tanh(kh))
+    h = np.full(nx, depth)
+    eta = (H / 2.0) * np.cos(k * x) + (k * H * H / 16.0) * math.cosh(kh) * (2.0 + math.cosh(2 * kh)) \
+        / math.sinh(kh) ** 3 * np.cos(2 * k * x)
+    d = h + eta
+    z = sigma[:, None] * d[None, :] - h[None, :]
+    zp = z + depth
+    a1 = G * H / (2.0 * om) / math.cosh(kh)
+    a2 = 3.0 * H * H * om / 32.0 / math.sinh(kh) ** 4
+    X = x[None, :]
+    u = a1 * k * np.cosh(k * zp) * np.cos(k * X) + a2 * 2 * k * np.cosh(2 * k * zp) * np.cos(2 * k * X)
+    w = a1 * k * np.sinh(k * zp) * np.sin(k * X) + a2 * 2 * k * np.sinh(2 * k * zp) * np.sin(2 * k * X)
+    c = om / k
+    dt = cfl * (L / nx) / c
+    return dict(name="stokes", nx=nx, nz=nz, L=L, h=h, eta=eta, u=u, w=w, dt=dt, omega=om, H=H)
+
+
+def stokes_rest_problem(nx=256, nz=17):
+    """A single Poisson problem at the Stokes-wave geometry, first stage from rest."""
+    s = stokes_wave(nx, nz)
+    L, H, k = s["L"], s["H"], 2.0 * math.pi / s["L"]
+    x, _ = nodes(nx, nz, L)
+    kh = k
+    a2 = (k * H * H / 16.0) * math.cosh(kh) * (2.0 + math.cosh(2 * kh)) / math.sinh(kh) ** 3
+    eta_x = -(H / 2.0) * k * np.sin(k * x) - a2 * 2 * k * np.sin(2 * k * x)
+    eta_xx = -(H / 2.0) * k * k * np.cos(k * x) - a2 * 4 * k * k * np.cos(2 * k * x)
+    b = rest_rhs(s["h"], np.zeros(nx), eta_x, eta_xx, nz)
+    return dict(name="stokes_rest", nx=nx, nz=nz, L=L, h=s["h"], eta_old=s["eta"],
+                eta_new=s["eta"].copy(), b=b)
