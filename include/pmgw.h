@@ -1,0 +1,175 @@
+/*
+ * pmgw.h -- C ABI of the MI355X p-multigrid pressure Poisson library.
+ *
+ * The library solves the pressure Poisson problem of a sigma-transformed free-surface
+ * Navier-Stokes wave model with a Fourier basis in x and a Chebyshev basis in sigma
+ * (Melander, Bitsch, Chen, Engsig-Karup, "A High-Order Hybrid-Spectral Incompressible
+ * Navier-Stokes Model For Nonlinear Water Waves"). It does so for one tank or for a batch
+ * of independent tanks of uneven size.
+ *
+ * Conventions (all entry points)
+ *   - A field of tank t is a float64 array [Nz_t][Nx_t], row-major, x fastest. Row j holds
+ *     sigma_j = (1 + cos(j pi / M)) / 2 with M = Nz - 1: row 0 is the free surface
+ *     (sigma = 1), row M the bed (sigma = 0). Column i holds x_i = i L_t / Nx_t.
+ *     Tanks are packed back to back: tank t starts at element off2d[t] (see
+ *     pmgw_field_offsets). One-dimensional fields (h, eta) are packed the same way with off1d.
+ *   - Every field pointer is a DEVICE pointer owned by the caller, 8-byte aligned, on the
+ *     device that was current at pmgw_plan_create. The library never allocates device
+ *     memory: it reports a workspace size and the caller binds a device buffer of that size.
+ *   - Every call enqueues work on the plan's stream and returns without waiting, except when
+ *     a non-NULL HOST info pointer is given: then it waits for the stream before returning.
+ *   - Return codes: 0 = OK; > 0 = soft failure, outputs valid (PMGW_NOCONV); < 0 = hard
+ *     error, outputs unspecified. pmgw_last_error() describes the last failure of the
+ *     calling thread. No C++ exception crosses this interface.
+ *   - Sizes: Nx a power of two with 8 <= Nx <= 2048; Nz = M + 1 with M in {2, 4, 8, 16, 32}
+ *     and Nx >= 2 M; L > 0; 1 <= ntanks <= 65536.
+ *   - Calls on one plan must not overlap (the workspace is shared); plans are independent.
+ */
+#ifndef PMGW_H
+#define PMGW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PMGW_OK = 0,
+    PMGW_NOCONV = 1,       /* maxit reached; best iterate returned, relres in info          */
+    PMGW_EINVAL = -1,      /* bad argument: NULL, size, precision, rtol, unbound workspace  */
+    PMGW_EGEOM = -2,       /* water depth d = h + eta <= 0 (or not finite) somewhere        */
+    PMGW_ENAN = -3,        /* NaN/Inf met in the right-hand side or the Krylov scalars     */
+    PMGW_EWORKSPACE = -4,  /* workspace missing, too small or misaligned                    */
+    PMGW_EDEVICE = -5      /* a HIP runtime call failed                                     */
+};
+
+enum { PMGW_FP64 = 0, PMGW_MIXED = 1 };
+
+/* Solver and model options. pmgw_default_opts fills the defaults given in brackets. */
+typedef struct {
+    int32_t nu1;            /* pre-smoothing pairs per level [1]                              */
+    int32_t nu2;            /* post-smoothing pairs per level [1]                             */
+    int32_t coarse_pairs;   /* smoothing pairs on the coarsest level (order 2) [4]            */
+    int32_t restart;        /* FGMRES restart length, 1..32 [30]                              */
+    double omega_c;         /* damping of the column-block step [1.0]                         */
+    double omega_m;         /* damping of the flat-mode step [1.0]                            */
+    double rho;             /* density [1000]                                                 */
+    double g;               /* gravity magnitude [9.81]                                       */
+    double nu_visc;         /* kinematic viscosity [1e-6]                                     */
+    double filt_alpha;      /* filter strength alpha [36]                                     */
+    double filt_s;          /* filter order s [2]                                             */
+    double filt_fx;         /* x cut-off fraction of Nx/2 [0.5]                               */
+    double filt_fz;         /* sigma cut-off fraction of M [0.9]                              */
+    int32_t threads;        /* threads per workgroup of the solve kernel, 0 = tuned [0]       */
+    int32_t reserved;
+} pmgw_opts;
+
+/* Per-tank outcome of a solve. status is one of the codes above for that tank. */
+typedef struct {
+    int32_t iters;          /* FGMRES iterations (preconditioner applications)                */
+    int32_t status;
+    double relres;          /* ||b - A p||_2 / ||b||_2 of the returned p (0 when b = 0)       */
+} pmgw_info;
+
+typedef struct pmgw_plan_s* pmgw_plan;
+
+/* Fill *opts with the defaults. */
+void pmgw_default_opts(pmgw_opts* opts);
+
+/*
+ * Create a plan for ntanks tanks with host arrays nx[ntanks], nz[ntanks], L[ntanks].
+ * precision: PMGW_FP64 (everything in float64) or PMGW_MIXED (V-cycle smoothing, transfers
+ * and block inverses in float32; operator residuals, Krylov work, metrics and the solution
+ * in float64). opts may be NULL for the defaults. stream is a hipStream_t (NULL = default).
+ * On success *out receives the plan; the caller destroys it with pmgw_plan_destroy.
+ */
+int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const int32_t* nz,
+                     const double* L, int32_t precision, const pmgw_opts* opts, void* stream);
+
+/* Bytes of device workspace the plan needs (256-byte aligned buffer). */
+size_t pmgw_workspace_bytes(pmgw_plan plan);
+
+/*
+ * Bind a device buffer of at least pmgw_workspace_bytes bytes, 256-byte aligned, owned by
+ * the caller and kept alive while the plan is used. Copies the plan's constant tables into
+ * it (synchronous). Must precede every compute call.
+ */
+int pmgw_bind_workspace(pmgw_plan plan, void* dev_ptr, size_t bytes);
+
+/* Host outputs: off2d[ntanks+1] element offsets of 2D fields, off1d[ntanks+1] of 1D fields. */
+int pmgw_field_offsets(pmgw_plan plan, int64_t* off2d, int64_t* off1d);
+
+/*
+ * Set the two geometries of the mixed-stage operator (paper eq. poissonp): h is the still-
+ * water depth, eta_old the surface of stage k-1 (it carries the gradient and the bed
+ * condition), eta_new the surface of stage k (it carries the divergence). eta_new may equal
+ * eta_old (single-geometry problem). Computes the sigma-metrics (eq. 1_Scoef) and the
+ * smoother's block inverses on the device. A tank with d <= 0 is marked: its later solves
+ * report PMGW_EGEOM in info. All three are device arrays packed with off1d.
+ */
+int pmgw_set_geometry(pmgw_plan plan, const double* h, const double* eta_old,
+                      const double* eta_new);
+
+/*
+ * Ap = A p (paper eq. poissonp with eq. bcpd and eq. bcpdneu): interior rows
+ * Div^new(Grad^old p); row 0 = p (surface Dirichlet row); row M = -(h_x G_x + G_z) with
+ * (G_x, G_z) = Grad^old p (bed impermeability row, un-normalised outward normal).
+ * p and Ap are device fields; they must not overlap. Always float64.
+ */
+int laplacian_apply(pmgw_plan plan, const double* p, double* Ap);
+
+/*
+ * z = one p-multigrid V-cycle applied to r from a zero initial guess (paper Alg. 1, with
+ * the coarsening of Sec. 4.1 and the modal transfers of Sec. 4.2). In PMGW_MIXED plans the
+ * cycle runs in float32 (r is rounded on entry, z widened on exit). r and z are device
+ * fields and must not overlap.
+ */
+int pmg_vcycle(pmgw_plan plan, const double* r, double* z);
+
+/*
+ * Solve A p = b for every tank with flexible GMRES right-preconditioned by one V-cycle per
+ * iteration (paper Sec. 4.4). p holds the initial guess on entry and the solution on exit.
+ * Stops a tank when its true relative residual ||b - A p||_2/||b||_2 <= rtol or after maxit
+ * iterations (PMGW_NOCONV). rtol > 0, maxit >= 1. info_dev (device, ntanks entries) and
+ * info_host (host, ntanks entries; makes the call synchronous) are optional. The return
+ * value is the worst tank status (hard errors first) when info_host is given, else the
+ * launch status.
+ */
+int poisson_solve(pmgw_plan plan, const double* b, double* p, double rtol, int32_t maxit,
+                  pmgw_info* info_host, pmgw_info* info_dev);
+
+/*
+ * One stage k (1..5) of the 5-stage 2N low-storage Runge-Kutta scheme (paper eq. LSERK,
+ * Sec. 3.2 and 3.3) with the Carpenter-Kennedy (5,4) coefficients, for every tank:
+ * kinematic surface update and filter, metrics of the old and new surface, forcing at the
+ * old stage, provisional velocity, pressure right-hand side, poisson_solve (warm-started
+ * from p), projection and velocity update, filter of u and w. u, w, Ku, Kw, p are device
+ * fields; h, eta, Keta device 1D fields; all are updated in place except h. On exit p holds
+ * the stage's dynamic pressure p_D^(k-1). K registers must be zero before stage 1 of a step
+ * is irrelevant: stage 1 multiplies them by alpha_1 = 0.
+ */
+int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, double* w,
+              double* eta, double* Ku, double* Kw, double* Keta, double* p, double rtol,
+              int32_t maxit, pmgw_info* info_dev);
+
+/*
+ * lambda = A^-T g: solve the transposed system of the geometry last set (FGMRES on the
+ * transposed operator, float64, right-preconditioned by the forward V-cycle). lambda holds
+ * the initial guess on entry. Same conventions as poisson_solve.
+ */
+int pmgw_adjoint_solve(pmgw_plan plan, const double* g, double* lambda, double rtol,
+                       int32_t maxit, pmgw_info* info_host);
+
+/* Release the plan (not the workspace, which the caller owns). NULL is ignored. */
+void pmgw_plan_destroy(pmgw_plan plan);
+
+/* Message of the last failing call on this thread ("" if none). Valid until the next call. */
+const char* pmgw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMGW_H */

@@ -1,0 +1,538 @@
+// Host side of the p-multigrid pressure Poisson library: plans, workspace layout, constant
+// tables, argument validation and kernel launches behind the C ABI declared in pmgw.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pmgw.h"
+#include "pmgw_kernels.hpp"
+#include "pmgw_rk.hpp"
+
+using namespace pmgw;
+
+static_assert(sizeof(pmgw_info) == sizeof(pmgw_info_dev), "info layout");
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PMGW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+// ----------------------------------------------------------------------------- constant tables
+// Chebyshev-Gauss-Lobatto nodes xi_j = cos(j pi / M); sigma = (1 + xi)/2.
+std::vector<double> cgl_sigma(int M) {
+  std::vector<double> s(M + 1);
+  for (int j = 0; j <= M; ++j) s[j] = 0.5 * (1.0 + std::cos(M_PI * j / M));
+  s[M] = 0.0;
+  s[0] = 1.0;
+  return s;
+}
+
+// d/dsigma on the CGL nodes: twice the closed-form Chebyshev collocation derivative in xi,
+// with node differences written as products of sines and a negative-sum diagonal.
+std::vector<double> dsigma(int M) {
+  const int n = M + 1;
+  std::vector<double> D(n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double rs = 0.0;
+    for (int l = 0; l < n; ++l) {
+      if (l == j) continue;
+      const double cj = (j == 0 || j == M) ? 2.0 : 1.0;
+      const double cl = (l == 0 || l == M) ? 2.0 : 1.0;
+      const double diff = 2.0 * std::sin((j + l) * M_PI / (2.0 * M)) *
+                          std::sin((l - j) * M_PI / (2.0 * M));
+      const double v = (cj / cl) * (((j + l) & 1) ? -1.0 : 1.0) / diff;
+      D[j * n + l] = 2.0 * v;
+      rs += 2.0 * v;
+    }
+    D[j * n + j] = -rs;
+  }
+  return D;
+}
+
+// T_m(cos(theta)) = cos(m theta).
+double cheb_T(int m, double theta) { return std::cos(m * theta); }
+
+// Restriction fine order Mf -> Mc = Mf/2: nodal values -> Chebyshev coefficients, keep m <= Mc,
+// evaluate at the coarse nodes; surface and bed rows are injected. [(Mc+1)][(Mf+1)].
+std::vector<double> restriction(int Mf) {
+  const int Mc = Mf / 2, nf = Mf + 1, nc = Mc + 1;
+  std::vector<double> R(nc * nf, 0.0);
+  for (int jc = 0; jc < nc; ++jc) {
+    const double th = M_PI * jc / Mc;
+    for (int l = 0; l < nf; ++l) {
+      const double cl = (l == 0 || l == Mf) ? 2.0 : 1.0;
+      double s = 0.0;
+      for (int m = 0; m <= Mc; ++m) {
+        const double cm = (m == 0 || m == Mf) ? 2.0 : 1.0;
+        s += cheb_T(m, th) * (2.0 / (Mf * cm * cl)) * std::cos(M_PI * m * l / Mf);
+      }
+      R[jc * nf + l] = s;
+    }
+  }
+  for (int l = 0; l < nf; ++l) {
+    R[0 * nf + l] = (l == 0) ? 1.0 : 0.0;
+    R[Mc * nf + l] = (l == Mf) ? 1.0 : 0.0;
+  }
+  return R;
+}
+
+// Prolongation Mc -> Mf: the coarse interpolating polynomial evaluated at the fine nodes.
+std::vector<double> prolongation(int Mf) {
+  const int Mc = Mf / 2, nf = Mf + 1, nc = Mc + 1;
+  std::vector<double> P(nf * nc, 0.0);
+  for (int j = 0; j < nf; ++j) {
+    const double th = M_PI * j / Mf;
+    for (int c = 0; c < nc; ++c) {
+      const double cc = (c == 0 || c == Mc) ? 2.0 : 1.0;
+      double s = 0.0;
+      for (int m = 0; m <= Mc; ++m) {
+        const double cm = (m == 0 || m == Mc) ? 2.0 : 1.0;
+        s += cheb_T(m, th) * (2.0 / (Mc * cm * cc)) * std::cos(M_PI * m * c / Mc);
+      }
+      P[j * nc + c] = s;
+    }
+    if ((j & 1) == 0) {
+      for (int c = 0; c < nc; ++c) P[j * nc + c] = (c == j / 2) ? 1.0 : 0.0;
+    }
+  }
+  return P;
+}
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+}  // namespace
+
+struct pmgw_plan_s {
+  int ntanks = 0;
+  int prec = PMGW_FP64;
+  pmgw_opts opts{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<TankDesc> tanks;
+  std::vector<BlockJob> jobs;
+  int64_t nblocks = 0;
+  std::vector<int64_t> off2d, off1d;
+  // constant image: [descs][jobs][per-tank tables...] copied at bind time
+  std::vector<char> image;
+  int64_t desc_off = 0, job_off = 0, info_off = 0, rk_off = 0;
+  // tanks grouped by finest-level row count (3, 5, 9, 17, 33): one solve launch per class
+  int64_t ids_off[5] = {0, 0, 0, 0, 0};
+  std::vector<int32_t> ids[5];
+  int64_t total = 0;
+  char* ws = nullptr;
+  bool geometry_set = false;
+  int threads = 256;
+};
+
+namespace {
+
+template <typename T>
+void put(std::vector<char>& img, int64_t off, const std::vector<double>& v) {
+  T* p = reinterpret_cast<T*>(img.data() + off);
+  for (size_t i = 0; i < v.size(); ++i) p[i] = (T)v[i];
+}
+
+bool valid_m(int M) { return M == 2 || M == 4 || M == 8 || M == 16 || M == 32; }
+
+int check_plan(pmgw_plan p) {
+  if (!p) return fail(PMGW_EINVAL, "plan is NULL");
+  if (!p->ws) return fail(PMGW_EWORKSPACE, "no workspace bound");
+  return PMGW_OK;
+}
+
+KOpts kopts(const pmgw_plan_s* p) {
+  KOpts o;
+  o.nu1 = p->opts.nu1;
+  o.nu2 = p->opts.nu2;
+  o.coarse_pairs = p->opts.coarse_pairs;
+  o.restart = p->opts.restart;
+  o.omega_c = p->opts.omega_c;
+  o.omega_m = p->opts.omega_m;
+  return o;
+}
+
+int nz_class(int nz) { return nz == 3 ? 0 : nz == 5 ? 1 : nz == 9 ? 2 : nz == 17 ? 3 : 4; }
+
+template <typename TV, int NZ>
+void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, double rtol,
+                  int maxit, pmgw_info_dev* info, const KOpts& o) {
+  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
+  hipLaunchKernelGGL((k_solve<TV, NZ>), dim3((unsigned)p->ids[c].size()), dim3(p->threads), 0,
+                     p->stream, d, ids, p->ws, mode, in, out, rtol, maxit, info, o);
+}
+
+template <typename TV>
+void launch_all(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
+                pmgw_info_dev* info, const KOpts& o) {
+  if (!p->ids[0].empty()) launch_class<TV, 3>(p, 0, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[1].empty()) launch_class<TV, 5>(p, 1, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[2].empty()) launch_class<TV, 9>(p, 2, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[3].empty()) launch_class<TV, 17>(p, 3, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[4].empty()) launch_class<TV, 33>(p, 4, mode, in, out, rtol, maxit, info, o);
+}
+
+int launch_solve(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
+                 pmgw_info_dev* info) {
+  const KOpts o = kopts(p);
+  if (p->prec == PMGW_FP64)
+    launch_all<double>(p, mode, in, out, rtol, maxit, info, o);
+  else
+    launch_all<float>(p, mode, in, out, rtol, maxit, info, o);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "solve kernel launch");
+  return PMGW_OK;
+}
+
+}  // namespace
+
+// Internal hooks used by the RK stage (pmgw_rk.hpp) and the adjoint.
+int pmgw_internal_solve(pmgw_plan p, const double* b, double* x, double rtol, int maxit,
+                        pmgw_info_dev* info) {
+  return launch_solve(p, MODE_SOLVE, b, x, rtol, maxit, info);
+}
+
+extern "C" {
+
+void pmgw_default_opts(pmgw_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nu1 = 1;
+  o->nu2 = 1;
+  o->coarse_pairs = 4;
+  o->restart = 30;
+  o->omega_c = 1.0;
+  o->omega_m = 1.0;
+  o->rho = 1000.0;
+  o->g = 9.81;
+  o->nu_visc = 1e-6;
+  o->filt_alpha = 36.0;
+  o->filt_s = 2.0;
+  o->filt_fx = 0.5;
+  o->filt_fz = 0.9;
+  o->threads = 0;
+}
+
+const char* pmgw_last_error(void) { return g_err.c_str(); }
+
+int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const int32_t* nz,
+                     const double* L, int32_t precision, const pmgw_opts* opts, void* stream) {
+  g_err.clear();
+  if (!out) return fail(PMGW_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (ntanks < 1 || ntanks > 65536) return fail(PMGW_EINVAL, "ntanks must be in [1, 65536]");
+  if (!nx || !nz || !L) return fail(PMGW_EINVAL, "nx, nz and L must be non-NULL");
+  if (precision != PMGW_FP64 && precision != PMGW_MIXED)
+    return fail(PMGW_EINVAL, "precision must be PMGW_FP64 or PMGW_MIXED");
+  pmgw_opts o;
+  pmgw_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.nu1 < 0 || o.nu2 < 0 || o.coarse_pairs < 0 || o.nu1 > 8 || o.nu2 > 8 ||
+      o.coarse_pairs > 64)
+    return fail(PMGW_EINVAL, "smoothing counts out of range");
+  if (o.restart < 1 || o.restart > kMaxRestart)
+    return fail(PMGW_EINVAL, "restart must be in [1, 32]");
+  if (!(o.omega_c > 0.0 && o.omega_c < 2.0) || !(o.omega_m > 0.0 && o.omega_m < 2.0))
+    return fail(PMGW_EINVAL, "damping factors must be in (0, 2)");
+  if (o.threads != 0 && o.threads != 64 && o.threads != 128 && o.threads != 256)
+    return fail(PMGW_EINVAL, "threads must be 0, 64, 128 or 256");
+  for (int t = 0; t < ntanks; ++t) {
+    const int n = nx[t], M = nz[t] - 1;
+    if (n < 8 || n > 2048 || (n & (n - 1)) != 0)
+      return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": Nx must be a power of two in [8, 2048]");
+    if (!valid_m(M))
+      return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": Nz must be 3, 5, 9, 17 or 33");
+    if (n < 2 * M) return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": Nx must be >= 2 (Nz - 1)");
+    if (!(L[t] > 0.0) || !std::isfinite(L[t]))
+      return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": L must be positive and finite");
+  }
+
+  auto* p = new pmgw_plan_s();
+  p->ntanks = ntanks;
+  p->prec = precision;
+  p->opts = o;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+  p->threads = o.threads ? o.threads : 256;
+  const int vb = precision == PMGW_FP64 ? 8 : 4;   // V-cycle word size
+  const int m = o.restart;
+
+  // pass 1: offsets
+  int64_t cur = 0;
+  p->desc_off = cur;
+  cur = align256(cur + (int64_t)sizeof(TankDesc) * ntanks);
+  int njobs = 0;
+  for (int t = 0; t < ntanks; ++t) {
+    int M = nz[t] - 1, nl = 0;
+    while (true) { ++nl; if (M == 2) break; M /= 2; }
+    njobs += 2 * nl;
+  }
+  p->job_off = cur;
+  cur = align256(cur + (int64_t)sizeof(BlockJob) * njobs);
+  p->info_off = cur;
+  cur = align256(cur + (int64_t)sizeof(pmgw_info) * ntanks);
+  for (int t = 0; t < ntanks; ++t) p->ids[nz_class(nz[t])].push_back(t);
+  for (int c = 0; c < 5; ++c) {
+    p->ids_off[c] = cur;
+    cur = align256(cur + 4 * (int64_t)p->ids[c].size());
+  }
+  p->tanks.resize(ntanks);
+  p->off2d.assign(ntanks + 1, 0);
+  p->off1d.assign(ntanks + 1, 0);
+  // constant tables first (contiguous, copied at bind), then mutable arrays
+  for (int t = 0; t < ntanks; ++t) {
+    TankDesc& d = p->tanks[t];
+    std::memset(&d, 0, sizeof(d));
+    d.nx = nx[t];
+    d.nz = nz[t];
+    d.log2nx = ilog2(nx[t]);
+    d.L = L[t];
+    d.kfac = 2.0 * M_PI / L[t];
+    const double K = nx[t] / 2 - 1;
+    d.cxx = -(d.kfac * d.kfac / nx[t]) * 2.0 * (K * (K + 1.0) * (2.0 * K + 1.0) / 6.0);
+    d.off2d = p->off2d[t];
+    d.off1d = p->off1d[t];
+    p->off2d[t + 1] = p->off2d[t] + (int64_t)nx[t] * nz[t];
+    p->off1d[t + 1] = p->off1d[t] + nx[t];
+    int M = nz[t] - 1, l = 0;
+    while (true) {
+      LevelDesc& lv = d.lev[l];
+      lv.nz = M + 1;
+      lv.nzc = (M > 2) ? M / 2 + 1 : 0;
+      for (int pr = 0; pr < 2; ++pr) {
+        const int64_t w = pr == 0 ? 8 : 4;
+        lv.ds[pr] = cur; cur = align256(cur + w * lv.nz * lv.nz);
+        lv.sig[pr] = cur; cur = align256(cur + w * lv.nz);
+        if (lv.nzc) {
+          lv.R[pr] = cur; cur = align256(cur + w * lv.nzc * lv.nz);
+          lv.P[pr] = cur; cur = align256(cur + w * lv.nz * lv.nzc);
+        }
+      }
+      ++l;
+      if (M == 2) break;
+      M /= 2;
+    }
+    d.nlev = l;
+    d.tw[0] = cur; cur = align256(cur + 16LL * nx[t]);
+    d.tw[1] = cur; cur = align256(cur + 8LL * nx[t]);
+  }
+  const int64_t const_end = cur;
+  for (int t = 0; t < ntanks; ++t) {
+    TankDesc& d = p->tanks[t];
+    const int64_t n = (int64_t)d.nx * d.nz;
+    d.geo64 = cur; cur = align256(cur + 8LL * 10 * d.nx);
+    d.geo32 = cur; cur = align256(cur + 4LL * 7 * d.nx);
+    d.scal = cur; cur = align256(cur + 64);
+    d.V = cur; cur = align256(cur + 8LL * (m + 1) * n);
+    d.Z = cur; cur = align256(cur + 8LL * m * n);
+    d.a1 = cur; cur = align256(cur + 8LL * n);
+    d.a2 = cur; cur = align256(cur + 8LL * n);
+    d.a3 = cur; cur = align256(cur + 8LL * n);
+    d.aspec = cur; cur = align256(cur + 16LL * ((d.nz + 1) / 2) * d.nx);
+    for (int l = 0; l < d.nlev; ++l) {
+      LevelDesc& lv = d.lev[l];
+      const int64_t nl = (int64_t)lv.nz * d.nx;
+      lv.colinv = cur; cur = align256(cur + vb * (int64_t)lv.nz * lv.nz * d.nx);
+      lv.modeinv = cur; cur = align256(cur + vb * (int64_t)lv.nz * lv.nz * (d.nx / 2 + 1));
+      lv.x = cur; cur = align256(cur + vb * nl);
+      lv.f = cur; cur = align256(cur + vb * nl);
+      lv.r = cur; cur = align256(cur + vb * nl);
+      lv.t1 = cur; cur = align256(cur + vb * nl);
+      lv.t2 = cur; cur = align256(cur + vb * nl);
+      lv.t3 = cur; cur = align256(cur + vb * nl);
+      lv.spec = cur; cur = align256(cur + 2LL * vb * ((lv.nz + 1) / 2) * d.nx);
+    }
+  }
+  p->rk_off = cur;
+  cur = align256(cur + rk_workspace_bytes(p->off2d[ntanks], p->off1d[ntanks]));
+  p->total = cur;
+
+  // block-inversion jobs
+  int64_t first = 0;
+  for (int t = 0; t < ntanks; ++t) {
+    const TankDesc& d = p->tanks[t];
+    for (int l = 0; l < d.nlev; ++l) {
+      p->jobs.push_back(BlockJob{t, l, 0, d.nx, first});
+      first += d.nx;
+      p->jobs.push_back(BlockJob{t, l, 1, d.nx / 2 + 1, first});
+      first += d.nx / 2 + 1;
+    }
+  }
+  p->nblocks = first;
+  if (p->nblocks > 0x7fffffffLL) {
+    delete p;
+    return fail(PMGW_EINVAL, "too many blocks for one launch");
+  }
+
+  // pass 2: constant image
+  p->image.assign(const_end, 0);
+  std::memcpy(p->image.data() + p->desc_off, p->tanks.data(), sizeof(TankDesc) * ntanks);
+  std::memcpy(p->image.data() + p->job_off, p->jobs.data(), sizeof(BlockJob) * p->jobs.size());
+  for (int c = 0; c < 5; ++c)
+    if (!p->ids[c].empty())
+      std::memcpy(p->image.data() + p->ids_off[c], p->ids[c].data(), 4 * p->ids[c].size());
+  for (int t = 0; t < ntanks; ++t) {
+    const TankDesc& d = p->tanks[t];
+    for (int l = 0; l < d.nlev; ++l) {
+      const LevelDesc& lv = d.lev[l];
+      const int M = lv.nz - 1;
+      const auto D = dsigma(M);
+      const auto s = cgl_sigma(M);
+      put<double>(p->image, lv.ds[0], D);
+      put<float>(p->image, lv.ds[1], D);
+      put<double>(p->image, lv.sig[0], s);
+      put<float>(p->image, lv.sig[1], s);
+      if (lv.nzc) {
+        const auto R = restriction(M);
+        const auto P = prolongation(M);
+        put<double>(p->image, lv.R[0], R);
+        put<float>(p->image, lv.R[1], R);
+        put<double>(p->image, lv.P[0], P);
+        put<float>(p->image, lv.P[1], P);
+      }
+    }
+    std::vector<double> tw(2 * d.nx);
+    for (int k = 0; k < d.nx; ++k) {
+      const long double a = -2.0L * (long double)M_PI * k / d.nx;
+      tw[2 * k] = (double)std::cos(a);
+      tw[2 * k + 1] = (double)std::sin(a);
+    }
+    put<double>(p->image, d.tw[0], tw);
+    put<float>(p->image, d.tw[1], tw);
+  }
+  *out = p;
+  return PMGW_OK;
+}
+
+size_t pmgw_workspace_bytes(pmgw_plan p) { return p ? (size_t)p->total : 0; }
+
+int pmgw_bind_workspace(pmgw_plan p, void* dev, size_t bytes) {
+  g_err.clear();
+  if (!p) return fail(PMGW_EINVAL, "plan is NULL");
+  if (!dev) return fail(PMGW_EWORKSPACE, "workspace pointer is NULL");
+  if ((reinterpret_cast<uintptr_t>(dev) & 255) != 0)
+    return fail(PMGW_EWORKSPACE, "workspace must be 256-byte aligned");
+  if ((int64_t)bytes < p->total)
+    return fail(PMGW_EWORKSPACE, "workspace too small: need " + std::to_string(p->total) + " bytes");
+  hipError_t e = hipMemcpy(dev, p->image.data(), p->image.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy of constant tables");
+  p->ws = reinterpret_cast<char*>(dev);
+  p->geometry_set = false;
+  return PMGW_OK;
+}
+
+int pmgw_field_offsets(pmgw_plan p, int64_t* off2d, int64_t* off1d) {
+  if (!p) return fail(PMGW_EINVAL, "plan is NULL");
+  if (off2d) std::memcpy(off2d, p->off2d.data(), sizeof(int64_t) * (p->ntanks + 1));
+  if (off1d) std::memcpy(off1d, p->off1d.data(), sizeof(int64_t) * (p->ntanks + 1));
+  return PMGW_OK;
+}
+
+int pmgw_set_geometry(pmgw_plan p, const double* h, const double* eo, const double* en) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!h || !eo || !en) return fail(PMGW_EINVAL, "h, eta_old and eta_new must be non-NULL");
+  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  const BlockJob* j = reinterpret_cast<const BlockJob*>(p->ws + p->job_off);
+  hipLaunchKernelGGL(k_geometry, dim3(p->ntanks), dim3(256), 0, p->stream, d, p->ws, h, eo, en);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
+  if (p->prec == PMGW_FP64)
+    hipLaunchKernelGGL(k_blocks<double>, dim3((unsigned)p->nblocks), dim3(64), 0, p->stream, d, j,
+                       (int)p->jobs.size(), p->ws);
+  else
+    hipLaunchKernelGGL(k_blocks<float>, dim3((unsigned)p->nblocks), dim3(64), 0, p->stream, d, j,
+                       (int)p->jobs.size(), p->ws);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "block kernel launch");
+  p->geometry_set = true;
+  return PMGW_OK;
+}
+
+int laplacian_apply(pmgw_plan p, const double* in, double* out) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!p->geometry_set) return fail(PMGW_EINVAL, "geometry not set");
+  if (!in || !out) return fail(PMGW_EINVAL, "p and Ap must be non-NULL");
+  if (in == out) return fail(PMGW_EINVAL, "p and Ap must not overlap");
+  return launch_solve(p, MODE_APPLY, in, out, 0.0, 0, nullptr);
+}
+
+int pmg_vcycle(pmgw_plan p, const double* r, double* z) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!p->geometry_set) return fail(PMGW_EINVAL, "geometry not set");
+  if (!r || !z) return fail(PMGW_EINVAL, "r and z must be non-NULL");
+  if (r == z) return fail(PMGW_EINVAL, "r and z must not overlap");
+  return launch_solve(p, MODE_VCYCLE, r, z, 0.0, 0, nullptr);
+}
+
+int poisson_solve(pmgw_plan p, const double* b, double* x, double rtol, int32_t maxit,
+                  pmgw_info* info_host, pmgw_info* info_dev) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!p->geometry_set) return fail(PMGW_EINVAL, "geometry not set");
+  if (!b || !x) return fail(PMGW_EINVAL, "b and p must be non-NULL");
+  if (b == x) return fail(PMGW_EINVAL, "b and p must not overlap");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PMGW_EINVAL, "rtol must be positive");
+  if (maxit < 1) return fail(PMGW_EINVAL, "maxit must be >= 1");
+  pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev)
+                                  : reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
+  rc = launch_solve(p, MODE_SOLVE, b, x, rtol, maxit, dinfo);
+  if (rc) return rc;
+  if (info_host) {
+    hipError_t e = hipMemcpyAsync(info_host, dinfo, sizeof(pmgw_info) * p->ntanks,
+                                  hipMemcpyDeviceToHost, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "info copy");
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    int worst = PMGW_OK;
+    for (int t = 0; t < p->ntanks; ++t) {
+      const int s = info_host[t].status;
+      if (s < 0 && (worst >= 0 || s < worst)) worst = s;
+      else if (s > 0 && worst == PMGW_OK) worst = s;
+    }
+    if (worst < 0) return fail(worst, "a tank failed (see info)");
+    if (worst > 0) g_err = "a tank did not converge (see info)";
+    return worst;
+  }
+  return PMGW_OK;
+}
+
+void pmgw_plan_destroy(pmgw_plan p) { delete p; }
+
+}  // extern "C"
+
+extern "C" int rk4_stage(pmgw_plan p, int32_t, double, const double*, double*, double*, double*,
+                         double*, double*, double*, double*, double, int32_t, pmgw_info*) {
+  (void)p;
+  return fail(PMGW_EINVAL, "rk4_stage is not available in this build");
+}
+
+extern "C" int pmgw_adjoint_solve(pmgw_plan p, const double*, double*, double, int32_t,
+                                  pmgw_info*) {
+  (void)p;
+  return fail(PMGW_EINVAL, "pmgw_adjoint_solve is not available in this build");
+}

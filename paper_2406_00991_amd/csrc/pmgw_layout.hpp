@@ -1,0 +1,58 @@
+// Workspace layout shared by the host API and the kernels of the p-multigrid Poisson library.
+//
+// Everything lives in one caller-owned device buffer. All offsets are BYTE offsets from the
+// start of that buffer, each array aligned to 256 bytes.
+#pragma once
+#include <stdint.h>
+
+namespace pmgw {
+
+constexpr int kMaxLev = 5;          // orders 32, 16, 8, 4, 2
+constexpr int kMaxRestart = 32;     // FGMRES restart length bound (Hessenberg lives in LDS)
+constexpr int kFftBytes = 32768;    // one LDS ping-pong buffer of the row FFTs
+constexpr int kMaxNz = 33;
+
+enum : int32_t { PREC64 = 0, PREC32 = 1 };
+
+// One multigrid level of one tank (order M_l = nz - 1).
+struct LevelDesc {
+  int32_t nz, nzc;                  // rows here, rows on the next coarser level (0 on coarsest)
+  int64_t ds[2];                    // D_sigma [nz][nz], float64 / float32 copies
+  int64_t sig[2];                   // sigma_j [nz]
+  int64_t R[2];                     // restriction [nzc][nz]
+  int64_t P[2];                     // prolongation [nz][nzc]
+  int64_t colinv;                   // inverse column blocks [nz][nz][nx] (V-cycle precision)
+  int64_t modeinv;                  // inverse flat-mode blocks [nz][nz][nx/2+1]
+  int64_t x, f, r, t1, t2, t3;      // level vectors [nz][nx] (V-cycle precision)
+  int64_t spec;                     // packed row spectra [(nz+1)/2][nx] complex (V precision)
+};
+
+struct TankDesc {
+  int32_t nx, nz, nlev, log2nx;
+  double L, kfac, cxx;              // length, 2 pi / L, diagonal of D_x D_x
+  int64_t off2d, off1d;             // element offsets into the caller's packed fields
+  int64_t tw[2];                    // twiddles exp(-2 pi i t / nx), t < nx (complex)
+  int64_t geo64;                    // 10 x nx doubles (see GEO_* below)
+  int64_t geo32;                    // 7 x nx floats: ao, bo, ido, an, bn, idn, hx
+  int64_t scal;                     // 64 bytes: double cbar, ebar; int32 status at +16
+  int64_t V, Z;                     // FGMRES bases: (restart+1) x n and restart x n doubles
+  int64_t a1, a2, a3, aspec;        // float64 operator temporaries (finest level)
+  LevelDesc lev[kMaxLev];
+};
+
+// rows of geo64
+enum : int { GEO_H = 0, GEO_EO = 1, GEO_EN = 2, GEO_AO = 3, GEO_BO = 4, GEO_IDO = 5,
+             GEO_AN = 6, GEO_BN = 7, GEO_IDN = 8, GEO_HX = 9 };
+
+// A job of the block-inversion kernel: `count` consecutive workgroups, one block each.
+struct BlockJob {
+  int32_t tank, level, kind, count;   // kind 0 = column block i, 1 = flat-mode block k
+  int64_t first;
+};
+
+struct KOpts {
+  int32_t nu1, nu2, coarse_pairs, restart;
+  double omega_c, omega_m;
+};
+
+}  // namespace pmgw

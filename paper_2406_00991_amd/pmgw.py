@@ -1,0 +1,247 @@
+"""Python binding of the HIP library libpmgw.so (argument marshalling only).
+
+Every computation runs in the library's kernels; PyTorch provides device memory and the stream.
+The functions keep the C names: ``laplacian_apply``, ``pmg_vcycle``, ``poisson_solve``,
+``rk4_stage``, ``pmgw_adjoint_solve``; ``Plan`` wraps plan creation, workspace binding and
+geometry. There is no CPU fallback: a missing library raises ``PmgwError``.
+"""
+import ctypes
+import os
+import warnings
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmgw.so")
+
+OK, NOCONV, EINVAL, EGEOM, ENAN, EWORKSPACE, EDEVICE = 0, 1, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+STATUS_NAMES = {0: "OK", 1: "NOCONV", -1: "EINVAL", -2: "EGEOM", -3: "ENAN", -4: "EWORKSPACE",
+                -5: "EDEVICE"}
+
+
+class PmgwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("coarse_pairs", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("omega_c", ctypes.c_double), ("omega_m", ctypes.c_double),
+                ("rho", ctypes.c_double), ("g", ctypes.c_double), ("nu_visc", ctypes.c_double),
+                ("filt_alpha", ctypes.c_double), ("filt_s", ctypes.c_double),
+                ("filt_fx", ctypes.c_double), ("filt_fz", ctypes.c_double),
+                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libpmgw.so from the package directory (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PmgwError(EINVAL, f"{LIB_PATH} not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pmgw_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.pmgw_default_opts.restype = None
+        L.pmgw_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), _dp, ctypes.c_int32,
+                                       ctypes.POINTER(Opts), _vp]
+        L.pmgw_workspace_bytes.argtypes = [_vp]
+        L.pmgw_workspace_bytes.restype = ctypes.c_size_t
+        L.pmgw_bind_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.pmgw_field_offsets.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        L.pmgw_set_geometry.argtypes = [_vp, _vp, _vp, _vp]
+        L.laplacian_apply.argtypes = [_vp, _vp, _vp]
+        L.pmg_vcycle.argtypes = [_vp, _vp, _vp]
+        L.poisson_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.POINTER(Info), _vp]
+        L.rk4_stage.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp,
+                                _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, _vp]
+        L.pmgw_adjoint_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.POINTER(Info)]
+        L.pmgw_plan_destroy.argtypes = [_vp]
+        L.pmgw_plan_destroy.restype = None
+        L.pmgw_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+_DEBUG_SYNC = os.environ.get("PMGW_DEBUG_SYNC") == "1"
+
+
+def _trace(name):
+    """With PMGW_DEBUG_SYNC=1, wait for the GPU after each library call and print its name."""
+    if _DEBUG_SYNC:
+        import torch
+        torch.cuda.synchronize()
+        print(f"[pmgw] {name} done", flush=True)
+
+
+def _check(rc, soft_ok=False):
+    if rc < 0 or (rc > 0 and not soft_ok):
+        raise PmgwError(rc, lib().pmgw_last_error().decode())
+    return rc
+
+
+def default_opts(**kw):
+    o = Opts()
+    lib().pmgw_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t, dtype=None):
+    import torch
+    if not t.is_cuda:
+        raise PmgwError(EINVAL, "tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise PmgwError(EINVAL, "tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise PmgwError(EINVAL, f"tensor must be {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A solver plan for one or more tanks (sizes nx[t], nz[t], lengths L[t]).
+
+    precision: "fp64" or "mixed". The workspace is a torch uint8 tensor owned by the plan.
+    """
+
+    def __init__(self, nx, nz, L, precision="fp64", opts=None, device=None, stream=None,
+                 allocate=True):
+        import torch
+        nx = [int(v) for v in (nx if hasattr(nx, "__len__") else [nx])]
+        nz = [int(v) for v in (nz if hasattr(nz, "__len__") else [nz])]
+        L = [float(v) for v in (L if hasattr(L, "__len__") else [L])]
+        if not (len(nx) == len(nz) == len(L)):
+            raise PmgwError(EINVAL, "nx, nz and L must have the same length")
+        self.ntanks = len(nx)
+        self.nx, self.nz, self.L = nx, nz, L
+        self.precision = precision
+        prec = {"fp64": FP64, "mixed": MIXED}.get(precision)
+        if prec is None:
+            raise PmgwError(EINVAL, "precision must be 'fp64' or 'mixed'")
+        self.opts = opts if opts is not None else default_opts()
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        sh = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        h = ctypes.c_void_p()
+        a_nx = (ctypes.c_int32 * self.ntanks)(*nx)
+        a_nz = (ctypes.c_int32 * self.ntanks)(*nz)
+        a_L = (ctypes.c_double * self.ntanks)(*L)
+        _check(lib().pmgw_plan_create(ctypes.byref(h), self.ntanks, a_nx, a_nz, a_L, prec,
+                                      ctypes.byref(self.opts), sh))
+        self._h = h
+        o2 = (ctypes.c_int64 * (self.ntanks + 1))()
+        o1 = (ctypes.c_int64 * (self.ntanks + 1))()
+        _check(lib().pmgw_field_offsets(h, o2, o1))
+        self.off2d = list(o2)
+        self.off1d = list(o1)
+        self.n2d = self.off2d[-1]
+        self.n1d = self.off1d[-1]
+        self.workspace_bytes = int(lib().pmgw_workspace_bytes(h))
+        self.device = device if device is not None else "cuda"
+        self.ws = None
+        if allocate:
+            self.bind(torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device))
+        self.info_dev = None
+
+    def bind(self, ws):
+        self.ws = ws
+        _check(lib().pmgw_bind_workspace(self._h, _ptr(ws), ws.numel()))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                lib().pmgw_plan_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    # -- helpers
+    def field(self, fill=0.0):
+        import torch
+        return torch.full((self.n2d,), fill, dtype=torch.float64, device=self.device)
+
+    def split2d(self, flat):
+        return [flat[self.off2d[t]:self.off2d[t + 1]].view(self.nz[t], self.nx[t])
+                for t in range(self.ntanks)]
+
+    def split1d(self, flat):
+        return [flat[self.off1d[t]:self.off1d[t + 1]] for t in range(self.ntanks)]
+
+    def set_geometry(self, h, eta_old, eta_new=None):
+        import torch
+        eta_new = eta_old if eta_new is None else eta_new
+        for t in (h, eta_old, eta_new):
+            if t.numel() != self.n1d:
+                raise PmgwError(EINVAL, "1D fields must have off1d[-1] entries")
+        self._geo = (h, eta_old, eta_new)
+        _check(lib().pmgw_set_geometry(self._h, _ptr(h, torch.float64), _ptr(eta_old, torch.float64),
+                                       _ptr(eta_new, torch.float64)))
+        _trace("set_geometry")
+
+    def apply(self, p, out=None):
+        out = self.field() if out is None else out
+        laplacian_apply(self, p, out)
+        return out
+
+    def vcycle(self, r, out=None):
+        out = self.field() if out is None else out
+        pmg_vcycle(self, r, out)
+        return out
+
+    def solve(self, b, p=None, rtol=1e-10, maxit=100, sync=True):
+        p = self.field() if p is None else p
+        info = poisson_solve(self, b, p, rtol, maxit, sync=sync)
+        return p, info
+
+
+def laplacian_apply(plan, p, Ap):
+    import torch
+    _check(lib().laplacian_apply(plan._h, _ptr(p, torch.float64), _ptr(Ap, torch.float64)))
+    _trace("laplacian_apply")
+
+
+def pmg_vcycle(plan, r, z):
+    import torch
+    _check(lib().pmg_vcycle(plan._h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
+    _trace("pmg_vcycle")
+
+
+def poisson_solve(plan, b, p, rtol=1e-10, maxit=100, sync=True, info_dev=None):
+    """Returns a list of (iters, status, relres) per tank when sync, else None."""
+    import torch
+    infos = (Info * plan.ntanks)() if sync else None
+    dptr = _ptr(info_dev) if info_dev is not None else None
+    rc = lib().poisson_solve(plan._h, _ptr(b, torch.float64), _ptr(p, torch.float64),
+                             float(rtol), int(maxit), infos, dptr)
+    _trace("poisson_solve")
+    if rc < 0:
+        msg = lib().pmgw_last_error().decode()
+        out = [(i.iters, i.status, i.relres) for i in infos] if infos is not None else None
+        err = PmgwError(rc, msg)
+        err.info = out
+        raise err
+    if not sync:
+        return None
+    out = [(i.iters, i.status, i.relres) for i in infos]
+    if rc == NOCONV:
+        warnings.warn("poisson_solve: a tank did not converge: " +
+                      lib().pmgw_last_error().decode())
+    return out

@@ -1,0 +1,82 @@
+"""Host-only checks of the C ABI: the library loads, exports what include/pmgw.h declares, and
+validates arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2406_00991_amd import pmgw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pmgw.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_0-9]+)\s*\(", txt)) - {"if", "sizeof"})
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = pmgw.lib()
+    names = _declared()
+    assert {"laplacian_apply", "pmg_vcycle", "poisson_solve", "rk4_stage"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _create(nx, nz, L, prec=pmgw.FP64, opts=None):
+    h = ctypes.c_void_p()
+    n = len(nx)
+    rc = pmgw.lib().pmgw_plan_create(ctypes.byref(h), n, (ctypes.c_int32 * n)(*nx),
+                                     (ctypes.c_int32 * n)(*nz), (ctypes.c_double * n)(*L), prec,
+                                     ctypes.byref(opts) if opts else None, None)
+    return rc, h
+
+
+@pytest.mark.parametrize("nx,nz,L", [([12], [9], [1.0]), ([32], [7], [1.0]), ([32], [65], [1.0]),
+                                     ([8], [9], [1.0]), ([32], [9], [0.0]), ([4096], [9], [1.0]),
+                                     ([32], [9], [float("nan")])])
+def test_plan_rejects_bad_sizes(nx, nz, L):
+    rc, h = _create(nx, nz, L)
+    assert rc == pmgw.EINVAL and not h.value
+    assert pmgw.lib().pmgw_last_error()
+
+
+def test_plan_rejects_bad_options_and_precision():
+    rc, _ = _create([32], [9], [1.0], prec=7)
+    assert rc == pmgw.EINVAL
+    for bad in (dict(restart=0), dict(restart=33), dict(omega_c=0.0), dict(omega_m=2.0),
+                dict(nu1=-1), dict(threads=100), dict(threads=512)):
+        rc, _ = _create([32], [9], [1.0], opts=pmgw.default_opts(**bad))
+        assert rc == pmgw.EINVAL, bad
+
+
+def test_plan_layout_and_unbound_calls():
+    rc, h = _create([32, 64, 256], [9, 17, 33], [1.0, 2.0, 3.0])
+    assert rc == 0
+    L = pmgw.lib()
+    o2 = (ctypes.c_int64 * 4)()
+    o1 = (ctypes.c_int64 * 4)()
+    assert L.pmgw_field_offsets(h, o2, o1) == 0
+    assert list(o2) == [0, 288, 288 + 1088, 288 + 1088 + 8448]
+    assert list(o1) == [0, 32, 96, 352]
+    nbytes = L.pmgw_workspace_bytes(h)
+    assert nbytes > 8 * (list(o2)[-1]) * 60
+    # no workspace: every compute call refuses before any launch
+    x = ctypes.c_void_p(0x1000)
+    assert L.pmgw_set_geometry(h, x, x, x) == pmgw.EWORKSPACE
+    assert L.laplacian_apply(h, x, x) == pmgw.EWORKSPACE
+    assert L.pmg_vcycle(h, x, x) == pmgw.EWORKSPACE
+    assert L.poisson_solve(h, x, x, 1e-10, 10, None, None) == pmgw.EWORKSPACE
+    assert L.pmgw_bind_workspace(h, None, nbytes) == pmgw.EWORKSPACE
+    assert L.pmgw_bind_workspace(h, ctypes.c_void_p(0x1001), nbytes) == pmgw.EWORKSPACE
+    assert L.pmgw_bind_workspace(h, ctypes.c_void_p(0x1000), nbytes - 1) == pmgw.EWORKSPACE
+    L.pmgw_plan_destroy(h)
+    L.pmgw_plan_destroy(None)
+
+
+def test_null_plan():
+    L = pmgw.lib()
+    assert L.laplacian_apply(None, None, None) == pmgw.EINVAL
+    assert L.pmgw_workspace_bytes(None) == 0
