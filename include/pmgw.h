@@ -62,7 +62,7 @@ typedef struct {
     double filt_s;          /* filter order s [2]                                             */
     double filt_fx;         /* x cut-off fraction of Nx/2 [0.5]                               */
     double filt_fz;         /* sigma cut-off fraction of M [0.9]                              */
-    int32_t threads;        /* threads per workgroup of the solve kernel, 0 = tuned [0]       */
+    int32_t threads;        /* threads per solve workgroup: 64, 128 or 256; 0 = 256 [0]      */
     int32_t reserved;
 } pmgw_opts;
 

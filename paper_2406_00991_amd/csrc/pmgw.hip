@@ -171,13 +171,21 @@ KOpts kopts(const pmgw_plan_s* p) {
 
 int nz_class(int nz) { return nz == 3 ? 0 : nz == 5 ? 1 : nz == 9 ? 2 : nz == 17 ? 3 : 4; }
 
+// Largest workgroup the solve kernel is compiled for (its register budget follows from it).
+constexpr int kSolveMaxThreads = 256;
+
 template <typename TV, int NZ>
 void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, double rtol,
                   int maxit, pmgw_info_dev* info, const KOpts& o) {
   const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
   const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
-  hipLaunchKernelGGL((k_solve<TV, NZ>), dim3((unsigned)p->ids[c].size()), dim3(p->threads), 0,
-                     p->stream, d, ids, p->ws, mode, in, out, rtol, maxit, info, o);
+  const int nt = (int)p->ids[c].size();
+  constexpr int MAXT = kSolveMaxThreads;
+  const int thr = p->opts.threads ? p->opts.threads : MAXT;
+  // Two halves of 32 KB of FFT LDS per workgroup: two workgroups fit on one CU.
+  const int fftb = 32768;
+  hipLaunchKernelGGL((k_solve<TV, NZ, MAXT>), dim3((unsigned)nt), dim3(thr), (size_t)(2 * fftb),
+                     p->stream, d, ids, p->ws, mode, in, out, rtol, maxit, info, o, fftb);
 }
 
 template <typename TV>
@@ -271,7 +279,7 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   p->opts = o;
   p->stream = reinterpret_cast<hipStream_t>(stream);
   if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
-  p->threads = o.threads ? o.threads : 256;
+  p->threads = o.threads;
   const int vb = precision == PMGW_FP64 ? 8 : 4;   // V-cycle word size
   const int m = o.restart;
 
@@ -453,7 +461,8 @@ int pmgw_set_geometry(pmgw_plan p, const double* h, const double* eo, const doub
   if (!h || !eo || !en) return fail(PMGW_EINVAL, "h, eta_old and eta_new must be non-NULL");
   const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
   const BlockJob* j = reinterpret_cast<const BlockJob*>(p->ws + p->job_off);
-  hipLaunchKernelGGL(k_geometry, dim3(p->ntanks), dim3(256), 0, p->stream, d, p->ws, h, eo, en);
+  hipLaunchKernelGGL(k_geometry, dim3(p->ntanks), dim3(256), (size_t)(2 * kGeoFftBytes), p->stream,
+                     d, p->ws, h, eo, en);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
   if (p->prec == PMGW_FP64)

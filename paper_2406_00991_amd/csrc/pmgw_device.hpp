@@ -16,10 +16,33 @@
 
 namespace pmgw {
 
+// Global-memory pointers: accesses through them compile to global (not flat) memory
+// instructions, which keeps field traffic off the counter that scalar and LDS loads wait on.
+#define PMGW_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+using gptr = PMGW_GLOBAL T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) { return (gptr<T>)p; }
+
 template <typename T>
 struct cpx {
   T re, im;
 };
+// Complex values in global memory, read and written member by member.
+template <typename T>
+__device__ __forceinline__ cpx<T> gld(gptr<const cpx<T>> p, int i) {
+  return {p[i].re, p[i].im};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> gld(gptr<cpx<T>> p, int i) {
+  return {p[i].re, p[i].im};
+}
+template <typename T>
+__device__ __forceinline__ void gst(gptr<cpx<T>> p, int i, cpx<T> v) {
+  p[i].re = v.re;
+  p[i].im = v.im;
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -31,6 +54,27 @@ __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re
 
 __device__ __forceinline__ int tid() { return (int)threadIdx.x; }
 __device__ __forceinline__ int nthr() { return (int)blockDim.x; }
+
+// Workgroup-uniform values passed through a function call arrive in vector registers; these
+// helpers move them back to scalar registers (every lane holds the same value) so that the
+// callee addresses its tables with scalar loads.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(u & 0xffffffffULL));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return reinterpret_cast<P*>(((unsigned long long)hi << 32) | lo);
+}
 
 // Sum over the workgroup; every thread returns the same value (fixed summation order).
 // `red` is LDS scratch of at least nthr()/64 doubles.
@@ -54,7 +98,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // unscaled. tw[t] = exp(-2 pi i t / N) for t < N.
 template <typename T, bool INV>
 __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int nrows, int N, int log2N,
-                           const cpx<T>* __restrict__ tw) {
+                           gptr<const cpx<T>> __restrict__ tw) {
   int p = 1;
   if (log2N & 1) {
     const int h = N >> 1, items = nrows << (log2N - 1);
@@ -80,7 +124,7 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int nrows, int N, int log2N,
       cpx<T> u0 = s[i], u1 = s[i + q], u2 = s[i + 2 * q], u3 = s[i + 3 * q];
       if (p > 1) {
         const int t = k * tstep;
-        cpx<T> w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t];
+        cpx<T> w1 = gld<T>(tw, t), w2 = gld<T>(tw, 2 * t), w3 = gld<T>(tw, 3 * t);
         if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
         u1 = cmul(u1, w1);
         u2 = cmul(u2, w2);
@@ -102,22 +146,174 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int nrows, int N, int log2N,
   return a;
 }
 
+// LDS staging buffer of the row FFTs: dynamic shared memory of 2 * fftb bytes (two ping-pong
+// halves for the workgroup-wide FFT; per-wavefront rows for the wavefront FFT). It is declared
+// at namespace scope so that every function of a kernel addresses it as LDS.
+extern __shared__ double g_fft_lds[];
+
 template <typename T>
-__device__ __forceinline__ int fft_cap() { return kFftBytes / (int)sizeof(cpx<T>); }
+__device__ __forceinline__ cpx<T>* fft_buf() {
+  return reinterpret_cast<cpx<T>*>(g_fft_lds);
+}
+
+template <typename T>
+__device__ __forceinline__ int fft_cap(int fftb) { return fftb / (int)sizeof(cpx<T>); }
+
+// Orders LDS accesses of one wavefront: every lane's earlier LDS writes are seen by the later
+// reads of the other lanes of the same wavefront (LDS executes a wavefront's operations in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The Stockham FFT of fft_lds for ONE row of length N (64 <= N <= 512) owned by one wavefront,
+// in place: each pass reads its inputs into registers (at most 8 complex values per lane),
+// synchronises the wavefront, and writes its outputs over them.
+template <typename T, bool INV>
+__device__ void fft_wave(cpx<T>* a, int N, int log2N, gptr<const cpx<T>> __restrict__ tw, int lane) {
+  cpx<T> r[8];
+  int p = 1;
+  if (log2N & 1) {
+    const int h = N >> 1;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int i = lane + 64 * it;
+      if (i < h) { r[2 * it] = a[i]; r[2 * it + 1] = a[i + h]; }
+    }
+    wave_sync();
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int i = lane + 64 * it;
+      if (i < h) {
+        a[2 * i] = cadd(r[2 * it], r[2 * it + 1]);
+        a[2 * i + 1] = csub(r[2 * it], r[2 * it + 1]);
+      }
+    }
+    wave_sync();
+    p = 2;
+  }
+  while (p < N) {
+    const int q = N >> 2;
+    const int tstep = N / (4 * p);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int i = lane + 64 * it;
+      if (i < q) {
+        r[4 * it] = a[i]; r[4 * it + 1] = a[i + q];
+        r[4 * it + 2] = a[i + 2 * q]; r[4 * it + 3] = a[i + 3 * q];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int i = lane + 64 * it;
+      if (i < q) {
+        const int k = i & (p - 1);
+        cpx<T> u0 = r[4 * it], u1 = r[4 * it + 1], u2 = r[4 * it + 2], u3 = r[4 * it + 3];
+        if (p > 1) {
+          const int t = k * tstep;
+          cpx<T> w1 = gld<T>(tw, t), w2 = gld<T>(tw, 2 * t), w3 = gld<T>(tw, 3 * t);
+          if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
+          u1 = cmul(u1, w1);
+          u2 = cmul(u2, w2);
+          u3 = cmul(u3, w3);
+        }
+        const cpx<T> v0 = cadd(u0, u2), v1 = csub(u0, u2), v2 = cadd(u1, u3);
+        const cpx<T> dd = csub(u1, u3);
+        const cpx<T> v3 = INV ? cpx<T>{-dd.im, dd.re} : cpx<T>{dd.im, -dd.re};
+        const int j = ((i - k) << 2) + k;
+        a[j] = cadd(v0, v2);
+        a[j + p] = cadd(v1, v3);
+        a[j + 2 * p] = csub(v0, v2);
+        a[j + 3 * p] = csub(v1, v3);
+      }
+    }
+    wave_sync();
+    p <<= 2;
+  }
+}
+
+// Load the packed row pair (ra, ra+1) of length N <= 512 into the wavefront's LDS row: all
+// global loads are issued before the first LDS write.
+template <typename T, class LD>
+__device__ __forceinline__ void wave_load_pair(cpx<T>* A, int N, int lane, int ra, int nrows,
+                                               LD ld) {
+  cpx<T> v[8];
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int n = lane + 64 * it;
+    if (n < N) v[it] = {ld(ra, n), (ra + 1 < nrows) ? ld(ra + 1, n) : T(0)};
+  }
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int n = lane + 64 * it;
+    if (n < N) A[n] = v[it];
+  }
+}
+
+// Hand the wavefront's LDS row back as the real rows (ra, ra+1): LDS reads first, then st().
+template <typename T, class ST>
+__device__ __forceinline__ void wave_store_pair(const cpx<T>* A, int N, int lane, int ra,
+                                                int nrows, ST st) {
+  cpx<T> v[8];
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int n = lane + 64 * it;
+    if (n < N) v[it] = A[n];
+  }
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int n = lane + 64 * it;
+    if (n < N) {
+      st(ra, n, v[it].re);
+      if (ra + 1 < nrows) st(ra + 1, n, v[it].im);
+    }
+  }
+}
+
+// Whether the per-wavefront FFT path applies: 64 <= N <= 512 and one N-row per wavefront fits.
+template <typename T>
+__device__ __forceinline__ bool fft_by_wave(int N, int fftb) {
+  return N >= 64 && N <= 512 && N * (nthr() >> 6) <= 2 * fft_cap<T>(fftb);
+}
 
 // D_x of `nrows` real rows (paper Sec. 3.5: F^-1(i kappa F f), Nyquist coefficient zeroed).
 // Two real rows are packed into one complex FFT (D_x is a real operator, so real and
 // imaginary parts stay separate). ld(j, i) reads input row j at column i; st(j, i, v) writes
-// the derivative. Ends with a barrier.
+// the derivative. fftb: bytes of one half of the FFT LDS buffer. Ends with a barrier.
 template <typename T, class LD, class ST>
-__device__ void dx_rows(int nrows, int N, int log2N, T kfac, const cpx<T>* __restrict__ tw,
-                        cpx<T>* lds, LD ld, ST st) {
-  const int cap = fft_cap<T>();
-  cpx<T>* A0 = lds;
-  cpx<T>* B0 = lds + cap;
-  const int rpb = cap >> log2N;
+__device__ void dx_rows(int nrows, int N, int log2N, T kfac, gptr<const cpx<T>> __restrict__ tw,
+                        int fftb, LD ld, ST st) {
   const int npairs = (nrows + 1) >> 1;
   const T scale = T(1) / T(N);
+  if (fft_by_wave<T>(N, fftb)) {
+    const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
+    cpx<T>* A = fft_buf<T>() + w * N;
+    for (int pp = w; pp < npairs; pp += nw) {
+      const int ra = 2 * pp;
+      wave_load_pair<T>(A, N, lane, ra, nrows, ld);
+      wave_sync();
+      fft_wave<T, false>(A, N, log2N, tw, lane);
+      for (int n = lane; n < N; n += 64) {
+        const int kk = (n <= (N >> 1)) ? n : n - N;
+        const T kap = (n == (N >> 1)) ? T(0) : kfac * T(kk) * scale;
+        const cpx<T> v = A[n];
+        A[n] = {-kap * v.im, kap * v.re};
+      }
+      wave_sync();
+      fft_wave<T, true>(A, N, log2N, tw, lane);
+      wave_store_pair<T>(A, N, lane, ra, nrows, st);
+      wave_sync();
+    }
+    __syncthreads();
+    return;
+  }
+  const int cap = fft_cap<T>(fftb);
+  cpx<T>* A0 = fft_buf<T>();
+  cpx<T>* B0 = A0 + cap;
+  const int rpb = cap >> log2N;
   for (int p0 = 0; p0 < npairs; p0 += rpb) {
     const int nb = min(rpb, npairs - p0);
     const int items = nb << log2N;
@@ -149,13 +345,27 @@ __device__ void dx_rows(int nrows, int N, int log2N, T kfac, const cpx<T>* __res
 
 // Forward FFT of real rows, packed in pairs, into spec[(nrows+1)/2][N] (global). Barrier at end.
 template <typename T, class LD>
-__device__ void rows_fft_to_global(int nrows, int N, int log2N, const cpx<T>* __restrict__ tw,
-                                   cpx<T>* lds, LD ld, cpx<T>* spec) {
-  const int cap = fft_cap<T>();
-  cpx<T>* A0 = lds;
-  cpx<T>* B0 = lds + cap;
-  const int rpb = cap >> log2N;
+__device__ void rows_fft_to_global(int nrows, int N, int log2N, gptr<const cpx<T>> __restrict__ tw,
+                                   int fftb, LD ld, gptr<cpx<T>> spec) {
   const int npairs = (nrows + 1) >> 1;
+  if (fft_by_wave<T>(N, fftb)) {
+    const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
+    cpx<T>* A = fft_buf<T>() + w * N;
+    for (int pp = w; pp < npairs; pp += nw) {
+      const int ra = 2 * pp;
+      wave_load_pair<T>(A, N, lane, ra, nrows, ld);
+      wave_sync();
+      fft_wave<T, false>(A, N, log2N, tw, lane);
+      for (int n = lane; n < N; n += 64) gst<T>(spec, pp * N + n, A[n]);
+      wave_sync();
+    }
+    __syncthreads();
+    return;
+  }
+  const int cap = fft_cap<T>(fftb);
+  cpx<T>* A0 = fft_buf<T>();
+  cpx<T>* B0 = A0 + cap;
+  const int rpb = cap >> log2N;
   for (int p0 = 0; p0 < npairs; p0 += rpb) {
     const int nb = min(rpb, npairs - p0);
     const int items = nb << log2N;
@@ -165,7 +375,7 @@ __device__ void rows_fft_to_global(int nrows, int N, int log2N, const cpx<T>* __
     }
     __syncthreads();
     cpx<T>* R = fft_lds<T, false>(A0, B0, nb, N, log2N, tw);
-    for (int it = tid(); it < items; it += nthr()) spec[(p0 << log2N) + it] = R[it];
+    for (int it = tid(); it < items; it += nthr()) gst<T>(spec, (p0 << log2N) + it, R[it]);
     __syncthreads();
   }
 }
@@ -173,17 +383,43 @@ __device__ void rows_fft_to_global(int nrows, int N, int log2N, const cpx<T>* __
 // Inverse FFT (unscaled) of packed spectra spec[(nrows+1)/2][N]; st(j, i, v) receives the real
 // rows. Barrier at end.
 template <typename T, class ST>
-__device__ void rows_ifft_from_global(int nrows, int N, int log2N, const cpx<T>* __restrict__ tw,
-                                      cpx<T>* lds, const cpx<T>* spec, ST st) {
-  const int cap = fft_cap<T>();
-  cpx<T>* A0 = lds;
-  cpx<T>* B0 = lds + cap;
-  const int rpb = cap >> log2N;
+__device__ void rows_ifft_from_global(int nrows, int N, int log2N, gptr<const cpx<T>> __restrict__ tw,
+                                      int fftb, gptr<const cpx<T>> spec, ST st) {
   const int npairs = (nrows + 1) >> 1;
+  if (fft_by_wave<T>(N, fftb)) {
+    const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
+    cpx<T>* A = fft_buf<T>() + w * N;
+    for (int pp = w; pp < npairs; pp += nw) {
+      const int ra = 2 * pp;
+      {
+        cpx<T> v[8];
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int n = lane + 64 * it;
+          if (n < N) v[it] = gld<T>(spec, pp * N + n);
+        }
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int n = lane + 64 * it;
+          if (n < N) A[n] = v[it];
+        }
+      }
+      wave_sync();
+      fft_wave<T, true>(A, N, log2N, tw, lane);
+      wave_store_pair<T>(A, N, lane, ra, nrows, st);
+      wave_sync();
+    }
+    __syncthreads();
+    return;
+  }
+  const int cap = fft_cap<T>(fftb);
+  cpx<T>* A0 = fft_buf<T>();
+  cpx<T>* B0 = A0 + cap;
+  const int rpb = cap >> log2N;
   for (int p0 = 0; p0 < npairs; p0 += rpb) {
     const int nb = min(rpb, npairs - p0);
     const int items = nb << log2N;
-    for (int it = tid(); it < items; it += nthr()) A0[it] = spec[(p0 << log2N) + it];
+    for (int it = tid(); it < items; it += nthr()) A0[it] = gld<T>(spec, (p0 << log2N) + it);
     __syncthreads();
     cpx<T>* S = fft_lds<T, true>(A0, B0, nb, N, log2N, tw);
     for (int it = tid(); it < items; it += nthr()) {
@@ -199,7 +435,7 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, const cpx<T>*
 // the nz real rows from the packed pairs, multiply by the inverse mode block (real, the same
 // for k and N-k), repack, and fold in the 1/N of the inverse FFT. minv is [NZ][NZ][N/2+1].
 template <typename T, int NZ>
-__device__ void mode_matvec(int N, const T* __restrict__ minv, cpx<T>* spec) {
+__device__ void mode_matvec(int N, gptr<const T> __restrict__ minv, gptr<cpx<T>> spec) {
   constexpr int NP = (NZ + 1) / 2;
   const int nh = (N >> 1) + 1;
   const T half = T(0.5), scale = T(1) / T(N);
@@ -208,11 +444,11 @@ __device__ void mode_matvec(int N, const T* __restrict__ minv, cpx<T>* spec) {
     cpx<T> rh[NZ];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      const cpx<T> z = spec[p * N + k], zc = spec[p * N + kc];
+      const cpx<T> z = gld<T>(spec, p * N + k), zc = gld<T>(spec, p * N + kc);
       rh[2 * p] = {half * (z.re + zc.re), half * (z.im - zc.im)};
       if (2 * p + 1 < NZ) rh[2 * p + 1] = {half * (z.im + zc.im), -half * (z.re - zc.re)};
     }
-#pragma unroll
+#pragma unroll 1
     for (int p = 0; p < NP; ++p) {
       cpx<T> s0 = {T(0), T(0)}, s1 = {T(0), T(0)};
       const int j0 = 2 * p, j1 = 2 * p + 1;
@@ -228,8 +464,8 @@ __device__ void mode_matvec(int N, const T* __restrict__ minv, cpx<T>* spec) {
         }
       }
       s0.re *= scale; s0.im *= scale; s1.re *= scale; s1.im *= scale;
-      spec[p * N + k] = {s0.re - s1.im, s0.im + s1.re};
-      if (k != 0 && k != (N >> 1)) spec[p * N + kc] = {s0.re + s1.im, s1.re - s0.im};
+      gst<T>(spec, p * N + k, cpx<T>{s0.re - s1.im, s0.im + s1.re});
+      if (k != 0 && k != (N >> 1)) gst<T>(spec, p * N + kc, cpx<T>{s0.re + s1.im, s1.re - s0.im});
     }
   }
 }
@@ -238,36 +474,55 @@ __device__ void mode_matvec(int N, const T* __restrict__ minv, cpx<T>* spec) {
 
 template <typename T>
 struct Geo {
-  const T *ao, *bo, *ido, *an, *bn, *idn, *hx;   // sigma_x = a + b sigma; ido = 1/d
+  gptr<const T> ao, bo, ido, an, bn, idn, hx;   // sigma_x = a + b sigma; ido = 1/d
 };
 
 template <typename T>
 struct Lev {
   int nz, nzc;
-  const T *Ds, *sig, *colinv, *modeinv, *R, *P;
-  T *x, *f, *r, *t1, *t2, *t3;
-  cpx<T>* spec;
+  gptr<const T> Ds, sig, colinv, modeinv, R, P;
+  gptr<T> x, f, r, t1, t2, t3;
+  gptr<cpx<T>> spec;
 };
 
 template <typename T>
 struct Ctx {
-  int nx, log2nx;
+  int nx, log2nx, fftb;
   T kfac;
-  const cpx<T>* tw;
+  gptr<const cpx<T>> tw;
   Geo<T> g;
-  cpx<T>* lds;
 };
+
+template <typename T>
+__device__ __forceinline__ Ctx<T> uni(const Ctx<T>& c) {
+  Ctx<T> u;
+  u.nx = uni(c.nx); u.log2nx = uni(c.log2nx); u.fftb = uni(c.fftb); u.kfac = uni(c.kfac); u.tw = uni(c.tw);
+  u.g.ao = uni(c.g.ao); u.g.bo = uni(c.g.bo); u.g.ido = uni(c.g.ido); u.g.an = uni(c.g.an);
+  u.g.bn = uni(c.g.bn); u.g.idn = uni(c.g.idn); u.g.hx = uni(c.g.hx);
+  return u;
+}
+
+template <typename T>
+__device__ __forceinline__ Lev<T> uni(const Lev<T>& L) {
+  Lev<T> u;
+  u.nz = uni(L.nz); u.nzc = uni(L.nzc);
+  u.Ds = uni(L.Ds); u.sig = uni(L.sig); u.colinv = uni(L.colinv); u.modeinv = uni(L.modeinv);
+  u.R = uni(L.R); u.P = uni(L.P);
+  u.x = uni(L.x); u.f = uni(L.f); u.r = uni(L.r); u.t1 = uni(L.t1); u.t2 = uni(L.t2);
+  u.t3 = uni(L.t3); u.spec = uni(L.spec);
+  return u;
+}
 
 // ----------------------------------------------------------------------------- column phases
 
 // out = D_sigma in, column by column.
 template <typename T, int NZ>
-__device__ void col_dsig(int nx, const T* __restrict__ Ds, const T* in, T* out) {
+__device__ void col_dsig(int nx, gptr<const T> __restrict__ Ds, gptr<const T> in, gptr<T> out) {
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZ];
 #pragma unroll
     for (int l = 0; l < NZ; ++l) v[l] = in[l * nx + i];
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < NZ; ++j) {
       T s = T(0);
 #pragma unroll
@@ -280,59 +535,60 @@ __device__ void col_dsig(int nx, const T* __restrict__ Ds, const T* in, T* out) 
 enum : int { FIN_APPLY = 0, FIN_RESID = 1, FIN_COLSTEP = 2 };
 
 // Last phase of the operator: A in = D_x G_x + sx_new D_s G_x + D_s G_z / d_new on interior
-// rows, row 0 = in (Dirichlet), row M = -(h_x G_x + G_z) (bed). gz, gx are G_z, G_x; dxgx holds
-// D_x G_x and is used as scratch. With sx_new = a_n + b_n sigma the interior rows are
+// rows, row 0 = in (Dirichlet), row M = -(h_x G_x + G_z) (bed), where per column
+// G_x = P_x + sx_old P_s and G_z = P_s / d_old are rebuilt in registers from ps = D_s in and
+// px = D_x in, and dxgx = D_x G_x. With sx_new = a_n + b_n sigma the interior rows are
 //   D_x G_x + D_s (a_n G_x + G_z / d_n) + b_n sigma D_s G_x,
-// evaluated in two column passes that each hold one column in registers. FIN_APPLY writes A in
-// to out; FIN_RESID writes f - A in; FIN_COLSTEP also applies x += omega B_i^-1 (f - A in)_i
-// column by column (x may alias in).
-template <typename T, int NZ, int MODE>
-__device__ __forceinline__ void col_finish(int nx, const T* __restrict__ Ds,
-                                           const T* __restrict__ sig, const Geo<T>& g,
-                                           const T* in, const T* gz, const T* gx, T* dxgx, T* out,
-                                           const T* f, T* x, const T* __restrict__ cinv,
-                                           T omega) {
+// both contractions taken in one pass over each row of D_s. FIN_APPLY writes A in to out;
+// FIN_RESID writes f - A in; FIN_COLSTEP also applies x += omega B_i^-1 (f - A in)_i column by
+// column (x may alias in).
+template <typename T, int NZ>
+__device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __restrict__ Ds,
+                                           gptr<const T> __restrict__ sig, const Geo<T>& g,
+                                           gptr<const T> in, gptr<const T> ps,
+                                           gptr<const T> px, gptr<const T> dxgx, gptr<T> out,
+                                           gptr<const T> f, gptr<T> x,
+                                           gptr<const T> __restrict__ cinv, T omega) {
   for (int i = tid(); i < nx; i += nthr()) {
-    const T an = g.an[i], bn = g.bn[i], idn = g.idn[i];
-    {
-      T u[NZ];
+    const T ao = g.ao[i], bo = g.bo[i], ido = g.ido[i];
+    const T an = g.an[i], bn = g.bn[i], idn = g.idn[i], hx = g.hx[i];
+    T gx[NZ], u[NZ];
+    T gzM = T(0);
 #pragma unroll
-      for (int l = 0; l < NZ; ++l) u[l] = an * gx[l * nx + i] + idn * gz[l * nx + i];
-#pragma unroll
-      for (int j = 1; j < NZ - 1; ++j) {
-        T s = T(0);
-#pragma unroll
-        for (int l = 0; l < NZ; ++l) s += Ds[j * NZ + l] * u[l];
-        dxgx[j * nx + i] += s;
-      }
+    for (int l = 0; l < NZ; ++l) {
+      const T a = ps[l * nx + i];
+      gx[l] = px[l * nx + i] + (ao + bo * sig[l]) * a;
+      const T gz = a * ido;
+      u[l] = an * gx[l] + idn * gz;
+      if (l == NZ - 1) gzM = gz;
     }
-    {
-      T v[NZ];
-#pragma unroll
-      for (int l = 0; l < NZ; ++l) v[l] = gx[l * nx + i];
-      const T bed = -(g.hx[i] * v[NZ - 1] + gz[(NZ - 1) * nx + i]);
-#pragma unroll
-      for (int j = 0; j < NZ; ++j) {
-        T o;
-        if (j == 0) {
-          o = in[i];
-        } else if (j == NZ - 1) {
-          o = bed;
-        } else {
-          T s = T(0);
-#pragma unroll
-          for (int l = 0; l < NZ; ++l) s += Ds[j * NZ + l] * v[l];
-          o = dxgx[j * nx + i] + bn * sig[j] * s;
-        }
-        if (MODE == FIN_APPLY) out[j * nx + i] = o;
-        else out[j * nx + i] = f[j * nx + i] - o;
-      }
+    const T bed = -(hx * gx[NZ - 1] + gzM);
+    const T top = in[i];
+    if (mode == FIN_APPLY) {
+      out[i] = top;
+      out[(NZ - 1) * nx + i] = bed;
+    } else {
+      out[i] = f[i] - top;
+      out[(NZ - 1) * nx + i] = f[(NZ - 1) * nx + i] - bed;
     }
-    if (MODE == FIN_COLSTEP) {
+#pragma unroll 1
+    for (int j = 1; j < NZ - 1; ++j) {
+      T s1 = T(0), s2 = T(0);
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) {
+        const T d = Ds[j * NZ + l];
+        s1 += d * u[l];
+        s2 += d * gx[l];
+      }
+      const T o = dxgx[j * nx + i] + s1 + bn * sig[j] * s2;
+      if (mode == FIN_APPLY) out[j * nx + i] = o;
+      else out[j * nx + i] = f[j * nx + i] - o;
+    }
+    if (mode == FIN_COLSTEP) {
       T r[NZ];
 #pragma unroll
       for (int l = 0; l < NZ; ++l) r[l] = out[l * nx + i];
-#pragma unroll
+#pragma unroll 1
       for (int j = 0; j < NZ; ++j) {
         T s = T(0);
 #pragma unroll
@@ -345,12 +601,13 @@ __device__ __forceinline__ void col_finish(int nx, const T* __restrict__ Ds,
 
 // x = omega B_i^-1 f_i (column step from a zero iterate: the residual is f).
 template <typename T, int NZ>
-__device__ void col_solve_zero(int nx, const T* __restrict__ cinv, const T* f, T* x, T omega) {
+__device__ void col_solve_zero(int nx, gptr<const T> __restrict__ cinv, gptr<const T> f,
+                               gptr<T> x, T omega) {
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZ];
 #pragma unroll
     for (int l = 0; l < NZ; ++l) v[l] = f[l * nx + i];
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < NZ; ++j) {
       T s = T(0);
 #pragma unroll
@@ -362,13 +619,13 @@ __device__ void col_solve_zero(int nx, const T* __restrict__ cinv, const T* f, T
 
 // fc = R r (restriction to the next coarser order, NZC = (NZ+1)/2 rows).
 template <typename T, int NZ>
-__device__ void col_restrict(int nx, const T* __restrict__ R, const T* r, T* fc) {
+__device__ void col_restrict(int nx, gptr<const T> __restrict__ R, gptr<const T> r, gptr<T> fc) {
   constexpr int NZC = (NZ + 1) / 2;
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZ];
 #pragma unroll
     for (int l = 0; l < NZ; ++l) v[l] = r[l * nx + i];
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < NZC; ++j) {
       T s = T(0);
 #pragma unroll
@@ -380,13 +637,14 @@ __device__ void col_restrict(int nx, const T* __restrict__ R, const T* r, T* fc)
 
 // x += P xc (prolongation from the next coarser order).
 template <typename T, int NZ>
-__device__ void col_prolong_add(int nx, const T* __restrict__ P, const T* xc, T* x) {
+__device__ void col_prolong_add(int nx, gptr<const T> __restrict__ P, gptr<const T> xc,
+                                gptr<T> x) {
   constexpr int NZC = (NZ + 1) / 2;
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZC];
 #pragma unroll
     for (int c = 0; c < NZC; ++c) v[c] = xc[c * nx + i];
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < NZ; ++j) {
       T s = T(0);
 #pragma unroll
@@ -399,94 +657,105 @@ __device__ void col_prolong_add(int nx, const T* __restrict__ P, const T* xc, T*
 // ----------------------------------------------------------------------------- operator
 
 // The composite operator on one level of NZ rows (paper eq. poissonp, eq. bcpd, eq. bcpdneu):
-//   A: t1 = D_s in                                        (column phase)
-//   B: t2 = G_x = D_x in + sx_old t1; t1 = G_z = t1/d_old (row FFTs + epilogue)
-//   C: t3 = D_x G_x                                       (row FFTs)
-//   D: finish (column phase, see col_finish)
-template <typename T, int NZ, int MODE>
-__device__ __noinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, const T* in, T* out,
-                                         const T* f, T* x, T omega) {
+//   A: t1 = P_s = D_s in                                   (column phase)
+//   B: t2 = P_x = D_x in                                   (row FFTs)
+//   C: t3 = D_x G_x with G_x = P_x + sx_old P_s            (row FFTs, G_x formed on load)
+//   D: finish (column phase, see col_finish; mode FIN_APPLY, FIN_RESID or FIN_COLSTEP)
+template <typename T, int NZ>
+__device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int mode,
+                                         gptr<const T> in, gptr<T> out, gptr<const T> f,
+                                         gptr<T> x, T omega) {
   const int nx = c.nx;
-  T* t1 = L.t1;
-  T* t2 = L.t2;
-  T* t3 = L.t3;
-  const T* sig = L.sig;
+  const gptr<T> t1 = L.t1;
+  const gptr<T> t2 = L.t2;
+  const gptr<T> t3 = L.t3;
+  const gptr<const T> sig = L.sig;
   const Geo<T> g = c.g;
   col_dsig<T, NZ>(nx, L.Ds, in, t1);
   __syncthreads();
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.lds,
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
              [=](int j, int i) { return in[j * nx + i]; },
-             [=](int j, int i, T v) {
-               const T ps = t1[j * nx + i];
-               t2[j * nx + i] = v + (g.ao[i] + g.bo[i] * sig[j]) * ps;
-               t1[j * nx + i] = ps * g.ido[i];
-             });
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.lds,
-             [=](int j, int i) { return t2[j * nx + i]; },
+             [=](int j, int i, T v) { t2[j * nx + i] = v; });
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
+             [=](int j, int i) {
+               return t2[j * nx + i] + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i];
+             },
              [=](int j, int i, T v) { t3[j * nx + i] = v; });
-  col_finish<T, NZ, MODE>(nx, L.Ds, sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega);
+  col_finish<T, NZ>(mode, nx, L.Ds, sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega);
   __syncthreads();
 }
 
-// One smoothing pair on a level: column-block step x += omega_c B^-1 (f - A x), then the
-// flat-mode step x += omega_m F^-1 Ahat^-1 F (f - A x). xzero: x is known to be zero.
-template <typename T, int NZ>
-__device__ __noinline__ void smooth_pair(const Ctx<T>& c, const Lev<T>& L, bool xzero,
-                                            T omega_c, T omega_m) {
-  const int nx = c.nx;
-  if (xzero) {
-    col_solve_zero<T, NZ>(nx, L.colinv, L.f, L.x, omega_c);
-    __syncthreads();
-  } else {
-    op_apply<T, NZ, FIN_COLSTEP>(c, L, L.x, L.r, L.f, L.x, omega_c);
-  }
-  op_apply<T, NZ, FIN_RESID>(c, L, L.x, L.r, L.f, nullptr, T(0));
-  const T* r = L.r;
-  rows_fft_to_global<T>(NZ, nx, c.log2nx, c.tw, c.lds,
-                        [=](int j, int i) { return r[j * nx + i]; }, L.spec);
-  mode_matvec<T, NZ>(nx, L.modeinv, L.spec);
-  __syncthreads();
-  T* x = L.x;
-  rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.tw, c.lds, L.spec,
-                           [=](int j, int i, T v) { x[j * nx + i] += omega_m * v; });
-}
-
-template <typename T>
-__device__ __forceinline__ void fill_zero(T* p, int n) {
-  for (int e = tid(); e < n; e += nthr()) p[e] = T(0);
+template <typename P>
+__device__ __forceinline__ void fill_zero(P p, int n) {
+  for (int e = tid(); e < n; e += nthr()) p[e] = 0;
 }
 
 // The V-cycle (paper Alg. 1) from a zero guess on the levels l, l+1, ..., whose row counts are
-// NZ, (NZ+1)/2, ..., 3 (order halves per level). lev(l) returns the Lev of level l; input
-// lev(l).f, output lev(l).x. The recursion is resolved at compile time.
+// NZ, (NZ+1)/2, ..., 3 (the order halves per level). lev(l) returns the Lev of level l; input
+// lev(l).f, output lev(l).x.
+//
+// One level runs a list of steps, each an operator application followed by an action:
+//   COL   column-block step   x += omega_c B^-1 (f - A x)        (from x = 0: x = omega_c B^-1 f)
+//   MODE  flat-mode step      x += omega_m F^-1 Ahat^-1 F (f - A x)
+//   DOWN  residual, restriction, the coarser V-cycle (a call), prolongation and correction
+// in the order nu1 x (COL, MODE), DOWN, nu2 x (COL, MODE); the coarsest level (3 rows) runs
+// coarse_pairs x (COL, MODE). The operator appears once in the loop body, which keeps each
+// level's code compact.
 template <typename T, int NZ, class LP>
-__device__ __noinline__ void vcycle(const Ctx<T>& c, const LP& lev, int l, const KOpts& o) {
+__device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
+  const Ctx<T> c = uni(c_);
+  const LP lev = uni(lev_);
+  const int l = uni(l_);
+  KOpts o;
+  o.nu1 = uni(o_.nu1); o.nu2 = uni(o_.nu2); o.coarse_pairs = uni(o_.coarse_pairs);
+  o.restart = uni(o_.restart); o.omega_c = uni(o_.omega_c); o.omega_m = uni(o_.omega_m);
   const int nx = c.nx;
   const T wc = T(o.omega_c), wm = T(o.omega_m);
-  const Lev<T> L = lev(l);
-  if constexpr (NZ == 3) {
-    for (int s = 0; s < o.coarse_pairs; ++s) smooth_pair<T, 3>(c, L, s == 0, wc, wm);
-    if (o.coarse_pairs == 0) {
-      fill_zero(L.x, 3 * nx);
+  const Lev<T> L = uni(lev(l));
+  enum { COL = 0, MODE = 1, DOWN = 2 };
+  const int npre = (NZ == 3) ? o.coarse_pairs : o.nu1;
+  const int npost = (NZ == 3) ? 0 : o.nu2;
+  const int nops = 2 * npre + ((NZ == 3) ? 0 : 1) + 2 * npost;
+  bool xzero = true;
+  for (int q = 0; q < nops; ++q) {
+    int kind;
+    if (q < 2 * npre) kind = (q & 1) ? MODE : COL;
+    else if (NZ != 3 && q == 2 * npre) kind = DOWN;
+    else kind = ((q - 2 * npre - 1) & 1) ? MODE : COL;
+    if (!(xzero && kind != MODE))
+      op_apply<T, NZ>(c, L, kind == COL ? FIN_COLSTEP : FIN_RESID, L.x, L.r, L.f, L.x, wc);
+    if (kind == COL) {
+      if (xzero) {
+        col_solve_zero<T, NZ>(nx, L.colinv, L.f, L.x, wc);
+        __syncthreads();
+        xzero = false;
+      }
+    } else if (kind == MODE) {
+      const gptr<const T> r = L.r;
+      rows_fft_to_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb,
+                            [=](int j, int i) { return r[j * nx + i]; }, L.spec);
+      mode_matvec<T, NZ>(nx, L.modeinv, L.spec);
       __syncthreads();
-    }
-  } else {
-    constexpr int NZC = (NZ + 1) / 2;
-    for (int s = 0; s < o.nu1; ++s) smooth_pair<T, NZ>(c, L, s == 0, wc, wm);
-    const T* rr = L.f;
-    if (o.nu1 > 0) {
-      op_apply<T, NZ, FIN_RESID>(c, L, L.x, L.r, L.f, nullptr, T(0));
-      rr = L.r;
+      const gptr<T> x = L.x;
+      rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb, L.spec,
+                               [=](int j, int i, T v) { x[j * nx + i] += wm * v; });
     } else {
-      fill_zero(L.x, NZ * nx);
+      if constexpr (NZ > 3) {
+        constexpr int NZC = (NZ + 1) / 2;
+        const Lev<T> C = uni(lev(l + 1));
+        if (xzero) fill_zero(L.x, NZ * nx);
+        col_restrict<T, NZ>(nx, L.R, xzero ? gptr<const T>(L.f) : gptr<const T>(L.r), C.f);
+        __syncthreads();
+        vcycle<T, NZC>(c, lev, l + 1, o);
+        col_prolong_add<T, NZ>(nx, L.P, C.x, L.x);
+        __syncthreads();
+        xzero = false;
+      }
     }
-    const Lev<T> C = lev(l + 1);
-    col_restrict<T, NZ>(nx, L.R, rr, C.f);
+  }
+  if (xzero) {
+    fill_zero(L.x, NZ * nx);
     __syncthreads();
-    vcycle<T, NZC>(c, lev, l + 1, o);
-    col_prolong_add<T, NZ>(nx, L.P, C.x, L.x);
-    __syncthreads();
-    for (int s = 0; s < o.nu2; ++s) smooth_pair<T, NZ>(c, L, false, wc, wm);
   }
 }
 

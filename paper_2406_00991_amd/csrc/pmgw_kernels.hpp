@@ -24,16 +24,25 @@ __device__ __forceinline__ T* mp(char* ws, int64_t off) {
 }
 
 template <typename T>
+__device__ __forceinline__ gptr<const T> gcp(const char* ws, int64_t off) {
+  return (gptr<const T>)(ws + off);
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> gmp(char* ws, int64_t off) {
+  return (gptr<T>)(ws + off);
+}
+
+template <typename T>
 __device__ Geo<T> make_geo(char* ws, const TankDesc& td) {
   Geo<T> g;
   if (std::is_same<T, double>::value) {
-    const T* b = cp<T>(ws, td.geo64);
+    const gptr<const T> b = gcp<T>(ws, td.geo64);
     const int nx = td.nx;
     g.ao = b + GEO_AO * nx; g.bo = b + GEO_BO * nx; g.ido = b + GEO_IDO * nx;
     g.an = b + GEO_AN * nx; g.bn = b + GEO_BN * nx; g.idn = b + GEO_IDN * nx;
     g.hx = b + GEO_HX * nx;
   } else {
-    const T* b = cp<T>(ws, td.geo32);
+    const gptr<const T> b = gcp<T>(ws, td.geo32);
     const int nx = td.nx;
     g.ao = b; g.bo = b + nx; g.ido = b + 2 * nx; g.an = b + 3 * nx; g.bn = b + 4 * nx;
     g.idn = b + 5 * nx; g.hx = b + 6 * nx;
@@ -46,12 +55,12 @@ __device__ Lev<T> make_lev(char* ws, const LevelDesc& d) {
   const int pr = std::is_same<T, double>::value ? 0 : 1;
   Lev<T> L;
   L.nz = d.nz; L.nzc = d.nzc;
-  L.Ds = cp<T>(ws, d.ds[pr]); L.sig = cp<T>(ws, d.sig[pr]);
-  L.R = cp<T>(ws, d.R[pr]); L.P = cp<T>(ws, d.P[pr]);
-  L.colinv = cp<T>(ws, d.colinv); L.modeinv = cp<T>(ws, d.modeinv);
-  L.x = mp<T>(ws, d.x); L.f = mp<T>(ws, d.f); L.r = mp<T>(ws, d.r);
-  L.t1 = mp<T>(ws, d.t1); L.t2 = mp<T>(ws, d.t2); L.t3 = mp<T>(ws, d.t3);
-  L.spec = mp<cpx<T>>(ws, d.spec);
+  L.Ds = gcp<T>(ws, d.ds[pr]); L.sig = gcp<T>(ws, d.sig[pr]);
+  L.R = gcp<T>(ws, d.R[pr]); L.P = gcp<T>(ws, d.P[pr]);
+  L.colinv = gcp<T>(ws, d.colinv); L.modeinv = gcp<T>(ws, d.modeinv);
+  L.x = gmp<T>(ws, d.x); L.f = gmp<T>(ws, d.f); L.r = gmp<T>(ws, d.r);
+  L.t1 = gmp<T>(ws, d.t1); L.t2 = gmp<T>(ws, d.t2); L.t3 = gmp<T>(ws, d.t3);
+  L.spec = gmp<cpx<T>>(ws, d.spec);
   return L;
 }
 
@@ -61,8 +70,8 @@ template <typename T>
 struct LevSet {
   char* ws;
   const TankDesc* td;
-  T* f0;
-  T* x0;
+  gptr<T> f0;
+  gptr<T> x0;
   __device__ Lev<T> operator()(int l) const {
     Lev<T> L = make_lev<T>(ws, td->lev[l]);
     if (l == 0 && f0) { L.f = f0; L.x = x0; }
@@ -70,7 +79,14 @@ struct LevSet {
   }
 };
 
+template <typename T>
+__device__ __forceinline__ LevSet<T> uni(const LevSet<T>& s) {
+  return LevSet<T>{uni(s.ws), uni(s.td), uni(s.f0), uni(s.x0)};
+}
+
 // ----------------------------------------------------------------------------- geometry kernel
+
+constexpr int kGeoFftBytes = 32768;   // the geometry kernel runs with 2 x 32 KB of FFT LDS
 //
 // One workgroup per tank: copies h, eta_old, eta_new, checks d > 0, and forms the
 // sigma-metrics of paper eq. 1_Scoef for both geometries: sigma_x = a + b sigma with
@@ -80,7 +96,6 @@ struct LevSet {
 __global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ descs, char* ws,
                                                   const double* h, const double* eo,
                                                   const double* en) {
-  __shared__ cpx<double> lds[2 * kFftBytes / sizeof(cpx<double>)];
   __shared__ double red[16];
   const TankDesc td = descs[blockIdx.x];
   const int nx = td.nx;
@@ -100,7 +115,7 @@ __global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ d
   }
   __syncthreads();
   // rows: 0 = h, 1 = d_old, 2 = d_new  ->  h_x (GEO_HX), d_x old (GEO_BO), d_x new (GEO_BN)
-  dx_rows<double>(3, nx, td.log2nx, td.kfac, cp<cpx<double>>(ws, td.tw[0]), lds,
+  dx_rows<double>(3, nx, td.log2nx, td.kfac, gcp<cpx<double>>(ws, td.tw[0]), kGeoFftBytes,
                   [=](int j, int i) {
                     return j == 0 ? G[GEO_H * nx + i]
                                   : G[GEO_H * nx + i] + G[(j == 1 ? GEO_EO : GEO_EN) * nx + i];
@@ -281,13 +296,12 @@ struct KrylovLds {
 // ids[]. mode MODE_APPLY: out = A in. MODE_VCYCLE: out = V-cycle(in). MODE_SOLVE: FGMRES(restart)
 // on A out = in with out as initial guess (paper Sec. 4.4): right preconditioning by one V-cycle,
 // modified Gram-Schmidt, Givens rotations, stop on the true relative residual.
-template <typename TV, int NZ>
-__global__ void __launch_bounds__(256) k_solve(const TankDesc* __restrict__ descs,
-                                               const int32_t* __restrict__ ids, char* ws,
-                                               int mode, const double* in, double* out,
-                                               double rtol, int maxit, pmgw_info_dev* info,
-                                               KOpts o) {
-  __shared__ cpx<double> lds_raw[2 * kFftBytes / sizeof(cpx<double>)];
+template <typename TV, int NZ, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ descs,
+                                                const int32_t* __restrict__ ids, char* ws,
+                                                int mode, const double* in, double* out,
+                                                double rtol, int maxit, pmgw_info_dev* info,
+                                                KOpts o, int fftb) {
   __shared__ KrylovLds K;
   const int tank = ids[blockIdx.x];
   const TankDesc& td = descs[tank];
@@ -302,24 +316,24 @@ __global__ void __launch_bounds__(256) k_solve(const TankDesc* __restrict__ desc
   }
 
   Ctx<double> c64;
-  c64.nx = nx; c64.log2nx = td.log2nx; c64.kfac = td.kfac;
-  c64.tw = cp<cpx<double>>(ws, td.tw[0]);
+  c64.nx = nx; c64.log2nx = td.log2nx; c64.kfac = td.kfac; c64.fftb = fftb;
+  c64.tw = gcp<cpx<double>>(ws, td.tw[0]);
   c64.g = make_geo<double>(ws, td);
-  c64.lds = lds_raw;
   Lev<double> A64 = make_lev<double>(ws, td.lev[0]);
-  A64.t1 = mp<double>(ws, td.a1); A64.t2 = mp<double>(ws, td.a2); A64.t3 = mp<double>(ws, td.a3);
-  A64.spec = mp<cpx<double>>(ws, td.aspec);
+  A64.t1 = gmp<double>(ws, td.a1); A64.t2 = gmp<double>(ws, td.a2);
+  A64.t3 = gmp<double>(ws, td.a3);
+  A64.spec = gmp<cpx<double>>(ws, td.aspec);
 
   Ctx<TV> cv;
-  cv.nx = nx; cv.log2nx = td.log2nx; cv.kfac = (TV)td.kfac;
-  cv.tw = cp<cpx<TV>>(ws, td.tw[std::is_same<TV, double>::value ? 0 : 1]);
+  cv.nx = nx; cv.log2nx = td.log2nx; cv.kfac = (TV)td.kfac; cv.fftb = fftb;
+  cv.tw = gcp<cpx<TV>>(ws, td.tw[std::is_same<TV, double>::value ? 0 : 1]);
   cv.g = make_geo<TV>(ws, td);
-  cv.lds = reinterpret_cast<cpx<TV>*>(lds_raw);
-  LevSet<TV> levs{ws, &td, nullptr, nullptr};
+  LevSet<TV> levs{ws, &td, gptr<TV>(nullptr), gptr<TV>(nullptr)};
   Lev<TV> L0 = levs(0);
 
   if (mode == MODE_APPLY) {
-    op_apply<double, NZ, FIN_APPLY>(c64, A64, b, x, nullptr, nullptr, 0.0);
+    op_apply<double, NZ>(c64, A64, FIN_APPLY, as_global(b), as_global(x),
+                         gptr<const double>(nullptr), gptr<double>(nullptr), 0.0);
     return;
   }
   if (mode == MODE_VCYCLE) {
@@ -349,7 +363,8 @@ __global__ void __launch_bounds__(256) k_solve(const TankDesc* __restrict__ desc
   }
   const int m = min(o.restart, kMaxRestart);
   for (;;) {
-    op_apply<double, NZ, FIN_RESID>(c64, A64, x, V, b, nullptr, 0.0);
+    op_apply<double, NZ>(c64, A64, FIN_RESID, as_global((const double*)x), as_global(V),
+                         as_global(b), gptr<double>(nullptr), 0.0);
     s = 0.0;
     for (int e = tid(); e < n; e += nthr()) s += V[e] * V[e];
     const double beta = sqrt(block_sum(s, K.red));
@@ -370,7 +385,8 @@ __global__ void __launch_bounds__(256) k_solve(const TankDesc* __restrict__ desc
       double* w = V + (int64_t)(j + 1) * n;
       // z_j = M^-1 v_j
       if constexpr (std::is_same<TV, double>::value) {
-        const LevSet<TV> lz{ws, &td, vj, zj};
+        const LevSet<TV> lz{ws, &td, as_global(reinterpret_cast<TV*>(vj)),
+                            as_global(reinterpret_cast<TV*>(zj))};
         vcycle<TV, NZ>(cv, lz, 0, o);
       } else {
         for (int e = tid(); e < n; e += nthr()) L0.f[e] = (TV)vj[e];
@@ -380,7 +396,8 @@ __global__ void __launch_bounds__(256) k_solve(const TankDesc* __restrict__ desc
         __syncthreads();
       }
       // w = A z_j
-      op_apply<double, NZ, FIN_APPLY>(c64, A64, zj, w, nullptr, nullptr, 0.0);
+      op_apply<double, NZ>(c64, A64, FIN_APPLY, as_global((const double*)zj), as_global(w),
+                           gptr<const double>(nullptr), gptr<double>(nullptr), 0.0);
       // modified Gram-Schmidt, each pass fuses the previous update with the next dot
       double hprev = 0.0;
       for (int i = 0; i <= j + 1; ++i) {
