@@ -239,3 +239,22 @@ def stokes_rest_problem(nx=256, nz=17):
     b = rest_rhs(s["h"], np.zeros(nx), eta_x, eta_xx, nz)
     return dict(name="stokes_rest", nx=nx, nz=nz, L=L, h=s["h"], eta_old=s["eta"],
                 eta_new=s["eta"].copy(), b=b)
+
+
+def airy_wave(nx=16, nz=9, depth=1.0, k=1.0, amp=1e-6, cfl=0.5):
+    """Small-amplitude (linear) progressive wave eta = a cos(kx), u = a w cosh(k(z+h))/sinh(kh)
+    cos(kx), w = a w sinh(k(z+h))/sinh(kh) sin(kx) at t = 0 with w^2 = g k tanh(kh); periodic
+    L = 2 pi / k, flat bed. Also returns the period and dt = cfl dx / c."""
+    L = 2.0 * math.pi / k
+    x, sigma = nodes(nx, nz, L)
+    om = math.sqrt(G * k * math.tanh(k * depth))
+    h = np.full(nx, depth)
+    eta = amp * np.cos(k * x)
+    d = h + eta
+    z = sigma[:, None] * d[None, :] - h[None, :]
+    zp = z + depth
+    u = amp * om * np.cosh(k * zp) / math.sinh(k * depth) * np.cos(k * x)[None, :]
+    w = amp * om * np.sinh(k * zp) / math.sinh(k * depth) * np.sin(k * x)[None, :]
+    c = om / k
+    return dict(name="airy", nx=nx, nz=nz, L=L, h=h, eta=eta, u=u, w=w, omega=om,
+                period=2.0 * math.pi / om, dt=cfl * (L / nx) / c, amp=amp, k=k)
