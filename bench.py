@@ -1,18 +1,23 @@
-"""Benchmark of the p-multigrid pressure Poisson path on one MI355X.
+"""Benchmark of the hybrid-spectral time-stepping hot path on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 
-Workload (the paper's time-stepping configuration): Nx = 256 Fourier x Nz = 17 Chebyshev, flat
-bed h = 1, periodic L = 2 pi, second-order Stokes wave kh = 1, H/L = 0.05. One step is one pass of
-the hot path: set the geometry of the stage (sigma-metrics and smoother block inverses) and solve
-the pressure Poisson problem to relative residual 1e-10 with FGMRES preconditioned by one
-p-multigrid V-cycle per iteration. The headline value is mixed precision (float32 V-cycle inside a
-float64 outer iteration); the float64 plan is timed alongside, with the difference of the two
-solutions.
+Workload: RK4 time stepping of a second-order Stokes wave, Nx = 256 Fourier x Nz = 17 Chebyshev
+points, flat bed h = 1, periodic L = 2 pi, kh = 1, H/L = 0.05, dt from CFL 0.5 on the linear
+phase speed. One step is one time step of the low-storage scheme: five stages, each with the
+kinematic surface update, the sigma-metrics of the new surface and the smoother block inverses,
+the forcing, the pressure Poisson solve (FGMRES to relative residual 1e-10, one p-multigrid
+V-cycle per iteration, warm-started from the previous stage's pressure), the projection and the
+filters. The headline value is Poisson solves per second in mixed precision (float32 V-cycle
+inside a float64 outer iteration); the float64 plan runs the same steps alongside, and the
+difference of the two final states is reported.
 
-Prints ONE JSON line (rank 0). See the design notes for the work model behind `roofline`.
+Prints ONE JSON line. `roofline` covers the dominant kernel (the solve kernel): algorithmic bytes
+per launch from the work model below over its mean launch duration, timed with HIP events on the
+plan's stream inside the timed region.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,6 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_solve_stokes256x17_traffic.json")
 
 
 # ----------------------------------------------------------------------------- work model
@@ -61,116 +67,183 @@ def vcycle_flops(nx, nz, nu1=1, nu2=1, coarse_pairs=4):
 
 def solve_flops(nx, nz, iters):
     n = nx * nz
-    per_it = vcycle_flops(nx, nz) + apply_flops(nx, nz) + sum(4 * n * (j + 2) for j in range(1))
-    arnoldi = sum(4.0 * n * (j + 2) for j in range(iters))
+    per_it = vcycle_flops(nx, nz) + apply_flops(nx, nz)
+    arnoldi = sum(4.0 * n * (j + 2) for j in range(int(round(iters))))
     return iters * per_it + arnoldi + 2 * apply_flops(nx, nz)
 
 
 def solve_bytes(nx, nz, iters, ws):
-    """Algorithmic bytes of one solve: each kernel phase reads its inputs once and writes its
-    outputs once; ws = word size of the V-cycle (8 float64, 4 mixed)."""
+    """Algorithmic bytes of one solve: each phase reads its inputs once and writes its outputs
+    once; per iteration j the Arnoldi step streams (2j + 4) float64 vectors, the V-cycle 19 words
+    per point of every level, and the preconditioned vector one; ws = word size of the V-cycle
+    (8 float64, 4 mixed)."""
     n = nx * nz
     nl = sum(nx * r for r in level_rows(nz))
     tot = 24 * n
-    for j in range(iters):
+    for j in range(int(round(iters))):
         tot += 16 * n + (2 * j + 4) * 8 * n + 19 * ws * nl + ws * n
     return tot + (iters * ws + 16) * n
 
 
-# ----------------------------------------------------------------------------- helpers
-def _plan(pr, precision):
+def kernel_source_hash():
+    """Hash of the HIP sources; the stored HBM counter readings are used only while it matches."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2406_00991_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, precision):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    ent = rec.get("kernels", {}).get(f"{kernel}/{precision}")
+    return None if ent is None else float(ent["bytes_per_launch"])
+
+
+# ----------------------------------------------------------------------------- GPU run
+class Tank:
+    """Device state of one tank and the stage loop through the C ABI."""
+
+    def __init__(self, wave, precision, capacity):
+        import torch
+
+        from paper_2406_00991_amd import pmgw
+        self.pmgw = pmgw
+        self.wave = wave
+        self.plan = pmgw.Plan([wave["nx"]], [wave["nz"]], [wave["L"]], precision=precision)
+        dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64,
+                                     device="cuda")
+        self.h, self.u, self.w, self.eta = (dev(wave[k]) for k in ("h", "u", "w", "eta"))
+        self.Ku = torch.zeros_like(self.u)
+        self.Kw = torch.zeros_like(self.u)
+        self.Keta = torch.zeros_like(self.eta)
+        self.p = torch.zeros_like(self.u)
+        self.info = pmgw.info_buffer(capacity)      # one record per stage
+        self.nstage = 0
+
+    def step(self, dt, rtol):
+        for k in range(1, 6):
+            rec = self.info[2 * self.nstage: 2 * self.nstage + 2]
+            self.pmgw.rk4_stage(self.plan, k, dt, self.h, self.u, self.w, self.eta, self.Ku,
+                                self.Kw, self.Keta, self.p, rtol=rtol, maxit=100, info_dev=rec)
+            self.nstage += 1
+
+    def infos(self, first, count):
+        return self.pmgw.read_info(self.info[2 * first: 2 * (first + count)])
+
+
+def run_precision(wave, precision, steps, warmup, rtol):
     import torch
-
-    from paper_2406_00991_amd import pmgw
-    plan = pmgw.Plan([pr["nx"]], [pr["nz"]], [pr["L"]], precision=precision)
-    dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64,
-                                 device="cuda")
-    return plan, dev(pr["h"]), dev(pr["eta_old"]), dev(pr["eta_new"]), dev(pr["b"])
-
-
-def _time_steps(plan, h, eo, en, b, steps, warmup, rtol):
-    import torch
-    p = plan.field()
+    T = Tank(wave, precision, 5 * (steps + warmup))
+    dt = wave["dt"]
     for _ in range(warmup):
-        plan.set_geometry(h, eo, en)
-        p.zero_()
-        plan.solve(b, p=p, rtol=rtol, maxit=100, sync=False)
+        T.step(dt, rtol)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
+    T.pmgw.profile_start(T.plan, 5 * steps)
     t0 = time.perf_counter()
-    for k in range(steps):
-        plan.set_geometry(h, eo, en)
-        p.zero_()
-        ev[k][0].record()
-        plan.solve(b, p=p, rtol=rtol, maxit=100, sync=False)
-        ev[k][1].record()
+    for _ in range(steps):
+        T.step(dt, rtol)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    solve_ms = float(np.mean([a.elapsed_time(c) for a, c in ev]))
-    info = plan.solve(b, p=p.zero_(), rtol=rtol, maxit=100)[1]
-    return wall, solve_ms, info, p
+    launches, tot_ms, max_ms = T.pmgw.profile_read(T.plan)
+    T.pmgw.profile_start(T.plan, 0)
+    infos = T.infos(5 * warmup, 5 * steps)
+    return dict(wall=wall, launches=launches, solve_ms=tot_ms / max(launches, 1), max_ms=max_ms,
+                iters=float(np.mean([i["iters"] for i in infos])),
+                max_iters=int(max(i["iters"] for i in infos)),
+                relres=float(max(i["relres"] for i in infos)),
+                status=sorted({i["status"] for i in infos}),
+                u=T.u.cpu().numpy(), w=T.w.cpu().numpy(), eta=T.eta.cpu().numpy(),
+                p=T.p.cpu().numpy())
 
 
-def cpu_baseline(pr, budget_s=12.0):
-    """The oracle as it stands: FGMRES with its own dense-step V-cycle, on the host's cores."""
+# ----------------------------------------------------------------------------- oracle timing
+def cpu_baseline(wave, budget_s=15.0):
+    """The oracle as it stands: its RK stage with the p-multigrid FGMRES solve (warm-started,
+    1e-10), from the same initial state, for about budget_s seconds on the host's cores."""
     from oracle import krylov
+    from oracle import lserk
     from oracle import operator as op
     from oracle import pmg
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count() or 1
-    go = op.Geometry(pr["h"], pr["eta_old"], pr["L"])
-    gn = op.Geometry(pr["h"], pr["eta_new"], pr["L"])
-    n_done, t0 = 0, time.perf_counter()
-    while True:
-        H = pmg.Hierarchy(pr["nx"], pr["nz"] - 1, go, gn, pmg.PmgOptions())
-        krylov.fgmres(lambda v: op.apply(v, go, gn), pr["b"], H, rtol=1e-10)
-        n_done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=n_done / dt, unit="solves/s", cores=cores, kind="oracle",
-                sample=f"{n_done} solves of the {pr['nx']}x{pr['nz']} problem (setup + FGMRES "
-                       f"to 1e-10), NumPy/SciPy float64")
+
+    def solve(b, g_old, g_new, p0):
+        H = pmg.Hierarchy(b.shape[1], b.shape[0] - 1, g_old, g_new, pmg.PmgOptions())
+        return krylov.fgmres(lambda v: op.apply(v, g_old, g_new), b, H, x0=p0, rtol=1e-10)[0]
+
+    s = lserk.State.rest_registers(wave["u"], wave["w"], wave["eta"])
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        lserk.stage(n % 5 + 1, wave["dt"], wave["h"], wave["L"], s, solve)
+        n += 1
+    el = time.perf_counter() - t0
+    return dict(value=n / el, unit="solves/s", cores=cores, kind="oracle",
+                sample=f"the first {n} RK stages (one pressure solve each) of the "
+                       f"{wave['nx']}x{wave['nz']} Stokes-wave run, NumPy/SciPy float64, "
+                       f"{el:.1f} s")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-mib", type=int, default=0,
+                    help="first run an elementwise negation of a float64 buffer of this size "
+                         "(reads and writes it once), the known-traffic kernel that scales the "
+                         "HBM counters of a profiled run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 (tanks shard across GPUs "
-              "without communication, see the design notes)", file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (--gpus 1); tanks would shard across "
+              "GPUs without communication", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
     import torch
 
     from paper_2406_00991_amd import workloads as wl
     torch.cuda.set_device(0)
-    pr = wl.stokes_rest_problem(256, 17)
+    if args.calibrate_mib > 0:
+        src = torch.ones(args.calibrate_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    wave = wl.stokes_wave(256, 17)
     rtol = 1e-10
-    res = {}
-    for prec in ("mixed", "fp64"):
-        plan, h, eo, en, b = _plan(pr, prec)
-        wall, solve_ms, info, p = _time_steps(plan, h, eo, en, b, args.steps, args.warmup, rtol)
-        res[prec] = dict(wall=wall, solve_ms=solve_ms, iters=info[0][0], relres=info[0][2],
-                         p=p.cpu().numpy())
-    mix, f64 = res["mixed"], res["fp64"]
-    delta = float(np.linalg.norm(mix["p"] - f64["p"]) / np.linalg.norm(f64["p"]))
-    nx, nz = pr["nx"], pr["nz"]
-    it = mix["iters"]
-    flops = solve_flops(nx, nz, it)
-    byts = solve_bytes(nx, nz, it, 4)
-    t_s = mix["solve_ms"] * 1e-3
-    achieved = flops / t_s / 1e12
+    res = {"mixed": run_precision(wave, "mixed", args.steps, args.warmup, rtol)}
+    print(f"# mixed: {args.steps} steps in {res['mixed']['wall']:.3f} s", file=sys.stderr,
+          flush=True)
+    if not args.no_fp64:
+        res["fp64"] = run_precision(wave, "fp64", args.steps, args.warmup, rtol)
+        print(f"# fp64: {args.steps} steps in {res['fp64']['wall']:.3f} s", file=sys.stderr,
+              flush=True)
+    mix = res["mixed"]
+    nx, nz = wave["nx"], wave["nz"]
+    solves = 5 * args.steps
+    t_launch = mix["solve_ms"] * 1e-3
+    byts = solve_bytes(nx, nz, mix["iters"], 4)
+    flops = solve_flops(nx, nz, mix["iters"])
+    achieved = byts / t_launch / 1e9
+    kname = "k_solve<float,17>"
     out = {
         "metric": "Poisson solves/s at rel. residual 1e-10 (mixed float32 V-cycle / float64 "
-                  "FGMRES)",
-        "value": args.steps / mix["wall"],
+                  "FGMRES), one per RK stage",
+        "value": solves / mix["wall"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -181,25 +254,36 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "stokes-wave pressure solve, Nx=256 x Nz=17, flat bed h=1, "
-                               "kh=1, H/L=0.05, first stage from rest, one tank",
-                   "precision": "mixed", "rtol": rtol},
-        "fp64": {"value": args.steps / f64["wall"], "unit": "solves/s",
-                 "ms_per_step": 1e3 * f64["wall"] / args.steps, "iters": f64["iters"],
-                 "relres": f64["relres"]},
-        "mixed": {"iters": mix["iters"], "relres": mix["relres"],
-                  "rel_diff_vs_fp64": delta},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_solve<float,17> (one workgroup per tank)",
-                     "launch_ms": mix["solve_ms"], "flops_per_launch": flops,
-                     "alg_bytes_per_launch": byts,
-                     "alg_GBps": byts / t_s / 1e9,
-                     "cus_used": 1,
-                     "frac_of_one_cu": achieved / (FP32_PEAK_TFLOPS / 256)},
+        "config": {"workload": "RK4 time stepping of a second-order Stokes wave, Nx=256 x Nz=17, "
+                               "flat bed h=1, L=2pi, kh=1, H/L=0.05, CFL 0.5, one tank, five "
+                               "warm-started pressure solves per step",
+                   "precision": "mixed", "rtol": rtol, "dt": wave["dt"]},
+        "solve": {"launches": mix["launches"], "mean_launch_ms": mix["solve_ms"],
+                  "max_launch_ms": mix["max_ms"], "mean_iters": mix["iters"],
+                  "max_iters": mix["max_iters"], "max_relres": mix["relres"],
+                  "status": mix["status"],
+                  "share_of_step": mix["solve_ms"] * solves / (1e3 * mix["wall"])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(kname, "mixed"),
+                     "kernel": kname + " (one workgroup per tank)",
+                     "alg_bytes_per_launch": byts, "launch_ms": mix["solve_ms"],
+                     "flops_per_launch": flops,
+                     "fp32_tflops": flops / t_launch / 1e12,
+                     "fp32_frac_of_one_cu": flops / t_launch / 1e12 / (FP32_PEAK_TFLOPS / 256),
+                     "cus_used": 1},
     }
+    if "fp64" in res:
+        f64 = res["fp64"]
+        rd = lambda k: float(np.abs(mix[k] - f64[k]).max() / np.abs(f64[k]).max())
+        out["fp64"] = {"value": solves / f64["wall"], "unit": "solves/s",
+                       "ms_per_step": 1e3 * f64["wall"] / args.steps,
+                       "mean_launch_ms": f64["solve_ms"], "mean_iters": f64["iters"],
+                       "max_relres": f64["relres"], "status": f64["status"],
+                       "mixed_speedup": f64["wall"] / mix["wall"]}
+        out["mixed_vs_fp64_final_state"] = {k: rd(k) for k in ("u", "w", "eta", "p")}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(pr)
+        out["cpu_baseline"] = cpu_baseline(wave)
     print(json.dumps(out))
 
 

@@ -147,8 +147,9 @@ int poisson_solve(pmgw_plan plan, const double* b, double* p, double rtol, int32
  * old stage, provisional velocity, pressure right-hand side, poisson_solve (warm-started
  * from p), projection and velocity update, filter of u and w. u, w, Ku, Kw, p are device
  * fields; h, eta, Keta device 1D fields; all are updated in place except h. On exit p holds
- * the stage's dynamic pressure p_D^(k-1). K registers must be zero before stage 1 of a step
- * is irrelevant: stage 1 multiplies them by alpha_1 = 0.
+ * the stage's dynamic pressure p_D^(k-1). The K registers need no reset between steps
+ * (stage 1 multiplies them by alpha_1 = 0) but must hold finite values. The workspace keeps
+ * the stage's intermediate fields; the plan's geometry is left at (eta^(k-1), eta^(k)).
  */
 int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, double* w,
               double* eta, double* Ku, double* Kw, double* Keta, double* p, double rtol,
@@ -164,6 +165,17 @@ int pmgw_adjoint_solve(pmgw_plan plan, const double* g, double* lambda, double r
 
 /* Release the plan (not the workspace, which the caller owns). NULL is ignored. */
 void pmgw_plan_destroy(pmgw_plan plan);
+
+/* Launch timing of the solve kernels, for measurement. capacity > 0 starts recording: every
+ * following poisson_solve call (also the one inside rk4_stage) records a pair of HIP events on
+ * the plan's stream around its kernel launches, for the first `capacity` calls; the previous
+ * record is cleared. capacity = 0 stops recording. Events are created on the host here, never
+ * device memory. Returns PMGW_EINVAL for capacity outside [0, 2^20]. */
+int pmgw_profile(pmgw_plan plan, int32_t capacity);
+
+/* Waits for the recorded events and returns the number of timed solve calls, their summed and
+ * their largest duration in milliseconds (host pointers). */
+int pmgw_profile_read(pmgw_plan plan, int32_t* launches, double* total_ms, double* max_ms);
 
 /* Message of the last failing call on this thread ("" if none). Valid until the next call. */
 const char* pmgw_last_error(void);

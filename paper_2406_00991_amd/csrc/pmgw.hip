@@ -118,6 +118,40 @@ int ilog2(int v) {
   return l;
 }
 
+// Exponential cut-off filter of paper Sec. 3.6 (with the damping sign): 1 for i <= Nc, else
+// exp(-alpha ((i - Nc)/(N + 1 - Nc))^s).
+double filter_factor(int i, int N, int Nc, double alpha, double s) {
+  if (i <= Nc) return 1.0;
+  return std::exp(-alpha * std::pow((i - Nc) / (N + 1.0 - Nc), s));
+}
+
+// Nodal sigma filter on the CGL nodes: Chebyshev coefficients scaled by the filter factors.
+std::vector<double> sigma_filter(int M, double frac, double alpha, double s) {
+  const int n = M + 1, Nc = (int)std::floor(frac * M);
+  std::vector<double> F(n * n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int l = 0; l < n; ++l) {
+      const double cl = (l == 0 || l == M) ? 2.0 : 1.0;
+      double acc = 0.0;
+      for (int m = 0; m <= M; ++m) {
+        const double cm = (m == 0 || m == M) ? 2.0 : 1.0;
+        acc += std::cos(M_PI * j * m / M) * filter_factor(m, M, Nc, alpha, s) *
+               (2.0 / (M * cm * cl)) * std::cos(M_PI * m * l / M);
+      }
+      F[j * n + l] = acc;
+    }
+  return F;
+}
+
+// Carpenter-Kennedy (5,4) coefficients of the 2N low-storage scheme.
+const double kCkAlpha[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                            -2404267990393.0 / 2016746695238.0,
+                            -3550918686646.0 / 2091501179385.0,
+                            -1275806237668.0 / 842570457699.0};
+const double kCkBeta[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                           1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                           2277821191437.0 / 14882151754819.0};
+
 }  // namespace
 
 struct pmgw_plan_s {
@@ -140,6 +174,14 @@ struct pmgw_plan_s {
   char* ws = nullptr;
   bool geometry_set = false;
   int threads = 256;
+  // launch timing of the solve kernels (pmgw_profile): one event pair per solve call
+  std::vector<hipEvent_t> ev0, ev1;
+  int prof_n = 0;
+  bool prof_on = false;
+  ~pmgw_plan_s() {
+    for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev1) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -201,12 +243,15 @@ void launch_all(pmgw_plan p, int mode, const double* in, double* out, double rto
 int launch_solve(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
                  pmgw_info_dev* info) {
   const KOpts o = kopts(p);
+  const bool timed = p->prof_on && mode == MODE_SOLVE && p->prof_n < (int)p->ev0.size();
+  if (timed) (void)hipEventRecord(p->ev0[p->prof_n], p->stream);
   if (p->prec == PMGW_FP64)
     launch_all<double>(p, mode, in, out, rtol, maxit, info, o);
   else
     launch_all<float>(p, mode, in, out, rtol, maxit, info, o);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "solve kernel launch");
+  if (timed) (void)hipEventRecord(p->ev1[p->prof_n++], p->stream);
   return PMGW_OK;
 }
 
@@ -256,6 +301,10 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   if (o.nu1 < 0 || o.nu2 < 0 || o.coarse_pairs < 0 || o.nu1 > 8 || o.nu2 > 8 ||
       o.coarse_pairs > 64)
     return fail(PMGW_EINVAL, "smoothing counts out of range");
+  if (!(o.rho > 0.0) || !(o.g >= 0.0) || !(o.nu_visc >= 0.0) || !(o.filt_alpha >= 0.0) ||
+      !(o.filt_s > 0.0) || !(o.filt_fx >= 0.0 && o.filt_fx <= 1.0) ||
+      !(o.filt_fz >= 0.0 && o.filt_fz <= 1.0))
+    return fail(PMGW_EINVAL, "physical or filter options out of range");
   if (o.restart < 1 || o.restart > kMaxRestart)
     return fail(PMGW_EINVAL, "restart must be in [1, 32]");
   if (!(o.omega_c > 0.0 && o.omega_c < 2.0) || !(o.omega_m > 0.0 && o.omega_m < 2.0))
@@ -341,6 +390,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     d.nlev = l;
     d.tw[0] = cur; cur = align256(cur + 16LL * nx[t]);
     d.tw[1] = cur; cur = align256(cur + 8LL * nx[t]);
+    d.filtx = cur; cur = align256(cur + 8LL * (nx[t] / 2 + 1));
+    d.filtz = cur; cur = align256(cur + 8LL * nz[t] * nz[t]);
   }
   const int64_t const_end = cur;
   for (int t = 0; t < ntanks; ++t) {
@@ -425,6 +476,12 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     }
     put<double>(p->image, d.tw[0], tw);
     put<float>(p->image, d.tw[1], tw);
+    std::vector<double> fx(d.nx / 2 + 1);
+    const int Nc = (int)std::floor(o.filt_fx * (d.nx / 2));
+    for (int k = 0; k <= d.nx / 2; ++k)
+      fx[k] = filter_factor(k, d.nx / 2, Nc, o.filt_alpha, o.filt_s);
+    put<double>(p->image, d.filtx, fx);
+    put<double>(p->image, d.filtz, sigma_filter(d.nz - 1, o.filt_fz, o.filt_alpha, o.filt_s));
   }
   *out = p;
   return PMGW_OK;
@@ -532,12 +589,113 @@ int poisson_solve(pmgw_plan p, const double* b, double* x, double rtol, int32_t 
 
 void pmgw_plan_destroy(pmgw_plan p) { delete p; }
 
+int pmgw_profile(pmgw_plan p, int32_t capacity) {
+  g_err.clear();
+  if (!p) return fail(PMGW_EINVAL, "plan is NULL");
+  if (capacity < 0 || capacity > (1 << 20)) return fail(PMGW_EINVAL, "capacity out of range");
+  p->prof_on = capacity > 0;
+  p->prof_n = 0;
+  while ((int)p->ev0.size() < capacity) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      p->prof_on = false;
+      return hip_fail(e, "hipEventCreate");
+    }
+    p->ev0.push_back(a);
+    p->ev1.push_back(b);
+  }
+  return PMGW_OK;
+}
+
+int pmgw_profile_read(pmgw_plan p, int32_t* launches, double* total_ms, double* max_ms) {
+  g_err.clear();
+  if (!p || !launches || !total_ms || !max_ms) return fail(PMGW_EINVAL, "NULL argument");
+  double tot = 0.0, mx = 0.0;
+  for (int i = 0; i < p->prof_n; ++i) {
+    hipError_t e = hipEventSynchronize(p->ev1[i]);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->ev0[i], p->ev1[i]);
+    if (e != hipSuccess) return hip_fail(e, "reading solve timings");
+    tot += ms;
+    mx = ms > mx ? ms : mx;
+  }
+  *launches = p->prof_n;
+  *total_ms = tot;
+  *max_ms = mx;
+  return PMGW_OK;
+}
+
 }  // extern "C"
 
-extern "C" int rk4_stage(pmgw_plan p, int32_t, double, const double*, double*, double*, double*,
-                         double*, double*, double*, double*, double, int32_t, pmgw_info*) {
-  (void)p;
-  return fail(PMGW_EINVAL, "rk4_stage is not available in this build");
+namespace {
+
+template <int NZ>
+void launch_rk(pmgw_plan p, int c, int which, const RkCoef& cf, const double* u, const double* w,
+               double* eta, double* Ku, double* Kw, double* Keta, const double* pr, double* uo,
+               double* wo, const RkBufs& rb) {
+  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
+  const unsigned nt = (unsigned)p->ids[c].size();
+  const int fftb = 32768;
+  if (which == 0)
+    hipLaunchKernelGGL(k_rk_pre<NZ>, dim3(nt), dim3(256), (size_t)(2 * fftb), p->stream, d, ids,
+                       p->ws, cf, u, w, eta, Keta, rb, fftb);
+  else if (which == 1)
+    hipLaunchKernelGGL(k_rk_force<NZ>, dim3(nt), dim3(256), (size_t)(2 * fftb), p->stream, d, ids,
+                       p->ws, cf, u, w, (const double*)Ku, (const double*)Kw, rb, fftb);
+  else
+    hipLaunchKernelGGL(k_rk_post<NZ>, dim3(nt), dim3(256), (size_t)(2 * fftb), p->stream, d, ids,
+                       p->ws, cf, pr, uo, wo, Ku, Kw, rb, fftb);
+}
+
+int launch_rk_all(pmgw_plan p, int which, const RkCoef& cf, double* u, double* w, double* eta,
+                  double* Ku, double* Kw, double* Keta, const double* pr, const RkBufs& rb) {
+  if (!p->ids[0].empty()) launch_rk<3>(p, 0, which, cf, u, w, eta, Ku, Kw, Keta, pr, u, w, rb);
+  if (!p->ids[1].empty()) launch_rk<5>(p, 1, which, cf, u, w, eta, Ku, Kw, Keta, pr, u, w, rb);
+  if (!p->ids[2].empty()) launch_rk<9>(p, 2, which, cf, u, w, eta, Ku, Kw, Keta, pr, u, w, rb);
+  if (!p->ids[3].empty()) launch_rk<17>(p, 3, which, cf, u, w, eta, Ku, Kw, Keta, pr, u, w, rb);
+  if (!p->ids[4].empty()) launch_rk<33>(p, 4, which, cf, u, w, eta, Ku, Kw, Keta, pr, u, w, rb);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
+  return PMGW_OK;
+}
+
+}  // namespace
+
+extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, double* u, double* w,
+                         double* eta, double* Ku, double* Kw, double* Keta, double* pr,
+                         double rtol, int32_t maxit, pmgw_info* info_dev) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (k < 1 || k > 5) return fail(PMGW_EINVAL, "stage k must be in 1..5");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PMGW_EINVAL, "dt must be positive");
+  if (!h || !u || !w || !eta || !Ku || !Kw || !Keta || !pr)
+    return fail(PMGW_EINVAL, "fields must be non-NULL");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PMGW_EINVAL, "rtol must be positive");
+  if (maxit < 1) return fail(PMGW_EINVAL, "maxit must be >= 1");
+  RkCoef cf;
+  cf.a = kCkAlpha[k - 1];
+  cf.b = kCkBeta[k - 1];
+  cf.dt = dt;
+  cf.rho = p->opts.rho;
+  cf.g = p->opts.g;
+  cf.nu = p->opts.nu_visc;
+  const RkBufs rb = rk_bufs(p->ws + p->rk_off, p->off2d[p->ntanks], p->off1d[p->ntanks]);
+  rc = launch_rk_all(p, 0, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
+  if (rc) return rc;
+  rc = pmgw_set_geometry(p, h, rb.eo, eta);
+  if (rc) return rc;
+  rc = launch_rk_all(p, 1, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
+  if (rc) return rc;
+  pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev)
+                                  : reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
+  rc = launch_solve(p, MODE_SOLVE, rb.b, pr, rtol, maxit, dinfo);
+  if (rc) return rc;
+  return launch_rk_all(p, 2, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
 }
 
 extern "C" int pmgw_adjoint_solve(pmgw_plan p, const double*, double*, double, int32_t,

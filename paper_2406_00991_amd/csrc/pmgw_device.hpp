@@ -279,15 +279,15 @@ __device__ __forceinline__ bool fft_by_wave(int N, int fftb) {
   return N >= 64 && N <= 512 && N * (nthr() >> 6) <= 2 * fft_cap<T>(fftb);
 }
 
-// D_x of `nrows` real rows (paper Sec. 3.5: F^-1(i kappa F f), Nyquist coefficient zeroed).
-// Two real rows are packed into one complex FFT (D_x is a real operator, so real and
-// imaginary parts stay separate). ld(j, i) reads input row j at column i; st(j, i, v) writes
-// the derivative. fftb: bytes of one half of the FFT LDS buffer. Ends with a barrier.
-template <typename T, class LD, class ST>
-__device__ void dx_rows(int nrows, int N, int log2N, T kfac, gptr<const cpx<T>> __restrict__ tw,
-                        int fftb, LD ld, ST st) {
+// A real spectral operator along x on `nrows` real rows: F^-1 (m_k F f) (paper Sec. 3.5 for D_x,
+// Sec. 3.6 for the filter). Two real rows are packed into one complex FFT; the multiplier must
+// satisfy m_{-k} = conj(m_k) (a real operator) so that real and imaginary parts stay separate. ld(j, i) reads input
+// row j at column i; sm(k, v) returns m_k v / N for the unscaled inverse FFT; st(j, i, v) writes
+// the result. fftb: bytes of one half of the FFT LDS buffer. Ends with a barrier.
+template <typename T, class LD, class SM, class ST>
+__device__ void spectral_rows(int nrows, int N, int log2N, gptr<const cpx<T>> __restrict__ tw,
+                              int fftb, LD ld, SM sm, ST st) {
   const int npairs = (nrows + 1) >> 1;
-  const T scale = T(1) / T(N);
   if (fft_by_wave<T>(N, fftb)) {
     const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
     cpx<T>* A = fft_buf<T>() + w * N;
@@ -296,12 +296,7 @@ __device__ void dx_rows(int nrows, int N, int log2N, T kfac, gptr<const cpx<T>> 
       wave_load_pair<T>(A, N, lane, ra, nrows, ld);
       wave_sync();
       fft_wave<T, false>(A, N, log2N, tw, lane);
-      for (int n = lane; n < N; n += 64) {
-        const int kk = (n <= (N >> 1)) ? n : n - N;
-        const T kap = (n == (N >> 1)) ? T(0) : kfac * T(kk) * scale;
-        const cpx<T> v = A[n];
-        A[n] = {-kap * v.im, kap * v.re};
-      }
+      for (int n = lane; n < N; n += 64) A[n] = sm(n, A[n]);
       wave_sync();
       fft_wave<T, true>(A, N, log2N, tw, lane);
       wave_store_pair<T>(A, N, lane, ra, nrows, st);
@@ -325,13 +320,7 @@ __device__ void dx_rows(int nrows, int N, int log2N, T kfac, gptr<const cpx<T>> 
     }
     __syncthreads();
     cpx<T>* R = fft_lds<T, false>(A0, B0, nb, N, log2N, tw);
-    for (int it = tid(); it < items; it += nthr()) {
-      const int n = it & (N - 1);
-      const int kk = (n <= (N >> 1)) ? n : n - N;
-      const T kap = (n == (N >> 1)) ? T(0) : kfac * T(kk) * scale;
-      const cpx<T> v = R[it];
-      R[it] = {-kap * v.im, kap * v.re};
-    }
+    for (int it = tid(); it < items; it += nthr()) R[it] = sm(it & (N - 1), R[it]);
     __syncthreads();
     cpx<T>* S = fft_lds<T, true>(R, R == A0 ? B0 : A0, nb, N, log2N, tw);
     for (int it = tid(); it < items; it += nthr()) {
@@ -341,6 +330,21 @@ __device__ void dx_rows(int nrows, int N, int log2N, T kfac, gptr<const cpx<T>> 
     }
     __syncthreads();
   }
+}
+
+// D_x of `nrows` real rows: the spectral multiplier i kappa_k / N with the Nyquist entry zeroed.
+template <typename T, class LD, class ST>
+__device__ __forceinline__ void dx_rows(int nrows, int N, int log2N, T kfac,
+                                        gptr<const cpx<T>> __restrict__ tw, int fftb, LD ld,
+                                        ST st) {
+  const T scale = T(1) / T(N);
+  spectral_rows<T>(nrows, N, log2N, tw, fftb, ld,
+                   [=](int n, cpx<T> v) {
+                     const int kk = (n <= (N >> 1)) ? n : n - N;
+                     const T kap = (n == (N >> 1)) ? T(0) : kfac * T(kk) * scale;
+                     return cpx<T>{-kap * v.im, kap * v.re};
+                   },
+                   st);
 }
 
 // Forward FFT of real rows, packed in pairs, into spec[(nrows+1)/2][N] (global). Barrier at end.
@@ -532,7 +536,9 @@ __device__ void col_dsig(int nx, gptr<const T> __restrict__ Ds, gptr<const T> in
   }
 }
 
-enum : int { FIN_APPLY = 0, FIN_RESID = 1, FIN_COLSTEP = 2 };
+// FIN_FULL: the interior formula on every row (no boundary rows): Div Grad of a field, used for
+// the viscous term of the momentum equations.
+enum : int { FIN_APPLY = 0, FIN_RESID = 1, FIN_COLSTEP = 2, FIN_FULL = 3 };
 
 // Last phase of the operator: A in = D_x G_x + sx_new D_s G_x + D_s G_z / d_new on interior
 // rows, row 0 = in (Dirichlet), row M = -(h_x G_x + G_z) (bed), where per column
@@ -562,17 +568,21 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __res
       u[l] = an * gx[l] + idn * gz;
       if (l == NZ - 1) gzM = gz;
     }
-    const T bed = -(hx * gx[NZ - 1] + gzM);
-    const T top = in[i];
-    if (mode == FIN_APPLY) {
-      out[i] = top;
-      out[(NZ - 1) * nx + i] = bed;
-    } else {
-      out[i] = f[i] - top;
-      out[(NZ - 1) * nx + i] = f[(NZ - 1) * nx + i] - bed;
+    const bool full = (mode == FIN_FULL);
+    if (!full) {
+      const T bed = -(hx * gx[NZ - 1] + gzM);
+      const T top = in[i];
+      if (mode == FIN_APPLY) {
+        out[i] = top;
+        out[(NZ - 1) * nx + i] = bed;
+      } else {
+        out[i] = f[i] - top;
+        out[(NZ - 1) * nx + i] = f[(NZ - 1) * nx + i] - bed;
+      }
     }
+    const int j0 = full ? 0 : 1, j1 = full ? NZ : NZ - 1;
 #pragma unroll 1
-    for (int j = 1; j < NZ - 1; ++j) {
+    for (int j = j0; j < j1; ++j) {
       T s1 = T(0), s2 = T(0);
 #pragma unroll
       for (int l = 0; l < NZ; ++l) {
@@ -581,7 +591,7 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __res
         s2 += d * gx[l];
       }
       const T o = dxgx[j * nx + i] + s1 + bn * sig[j] * s2;
-      if (mode == FIN_APPLY) out[j * nx + i] = o;
+      if (mode == FIN_APPLY || full) out[j * nx + i] = o;
       else out[j * nx + i] = f[j * nx + i] - o;
     }
     if (mode == FIN_COLSTEP) {

@@ -32,6 +32,8 @@ struct TankDesc {
   double L, kfac, cxx;              // length, 2 pi / L, diagonal of D_x D_x
   int64_t off2d, off1d;             // element offsets into the caller's packed fields
   int64_t tw[2];                    // twiddles exp(-2 pi i t / nx), t < nx (complex)
+  int64_t filtx;                    // x-filter factors F(|k|), k = 0..nx/2 (float64)
+  int64_t filtz;                    // sigma-filter matrix [nz][nz] on the finest level (float64)
   int64_t geo64;                    // 10 x nx doubles (see GEO_* below)
   int64_t geo32;                    // 7 x nx floats: ao, bo, ido, an, bn, idn, hx
   int64_t scal;                     // 64 bytes: double cbar, ebar; int32 status at +16

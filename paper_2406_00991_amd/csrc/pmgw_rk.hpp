@@ -1,7 +1,227 @@
-// Runge-Kutta stage and adjoint entry points (filled in below the solver).
+// Kernels of one low-storage Runge-Kutta stage with the pressure projection (paper Sec. 3.1-3.3,
+// Sec. 3.6), float64, one workgroup per tank, launched per finest-level row count NZ:
+//
+//   k_rk_pre    surface: eta_t = -u~ D_x eta + w~; K_eta <- a K_eta + dt eta_t;
+//               eta <- filter_x(eta + b K_eta); the old surface is kept for the metrics.
+//   (geometry)  sigma-metrics of the old and new surface and the smoother blocks.
+//   k_rk_force  forcing at the old stage, F_u = -u D_x u - w_s D_s u - g D_x eta + nu Div Grad u,
+//               F_w = -u D_x w - w_s D_s w + nu Div Grad w with w_s = sigma_t + u sigma_x + w/d,
+//               sigma_t = -sigma eta_t / d; provisional u* = u + b (a K_u + dt F_u), w*; right-hand
+//               side rho/(b dt) Div^new(u*, w*) inside, 0 on the surface row and
+//               -rho/(b dt)(h_x u* + w*) on the bed row (eq. poissonp, eq. bcpd, eq. bcpdneu).
+//   (solve)     flexible GMRES / p-multigrid for the dynamic pressure p.
+//   k_rk_post   (G_x, G_z) = Grad^old p; K_u <- a K_u + dt (F_u - G_x/rho), K_w likewise;
+//               u <- filter(u + b K_u), w <- filter(w + b K_w) in x and sigma.
 #pragma once
 #include <stdint.h>
 
+#include "pmgw_kernels.hpp"
+
 namespace pmgw {
-inline int64_t rk_workspace_bytes(int64_t n2d, int64_t n1d) { (void)n2d; (void)n1d; return 256; }
+
+// Packed workspace of the stage: 1D arrays of n1d doubles, 2D arrays of n2d doubles.
+struct RkBufs {
+  double *eo, *etat, *etax;
+  double *Fu, *Fw, *us, *ws, *b, *r1, *r2;
+};
+
+inline int64_t rk_align(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+inline int64_t rk_workspace_bytes(int64_t n2d, int64_t n1d) {
+  return 3 * rk_align(8 * n1d) + 7 * rk_align(8 * n2d);
+}
+
+inline RkBufs rk_bufs(char* base, int64_t n2d, int64_t n1d) {
+  RkBufs r;
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    double* p = reinterpret_cast<double*>(base + o);
+    o += rk_align(bytes);
+    return p;
+  };
+  r.eo = take(8 * n1d);
+  r.etat = take(8 * n1d);
+  r.etax = take(8 * n1d);
+  r.Fu = take(8 * n2d);
+  r.Fw = take(8 * n2d);
+  r.us = take(8 * n2d);
+  r.ws = take(8 * n2d);
+  r.b = take(8 * n2d);
+  r.r1 = take(8 * n2d);
+  r.r2 = take(8 * n2d);
+  return r;
+}
+
+struct RkCoef {
+  double a, b, dt, rho, g, nu;
+};
+
+// float64 context of a tank: metrics of the geometry last set, finest-level constants.
+__device__ __forceinline__ void rk_ctx(char* ws, const TankDesc& td, int fftb, Ctx<double>& c,
+                                       Lev<double>& A) {
+  c.nx = td.nx;
+  c.log2nx = td.log2nx;
+  c.kfac = td.kfac;
+  c.fftb = fftb;
+  c.tw = gcp<cpx<double>>(ws, td.tw[0]);
+  c.g = make_geo<double>(ws, td);
+  A = make_lev<double>(ws, td.lev[0]);
+  A.t1 = gmp<double>(ws, td.a1);
+  A.t2 = gmp<double>(ws, td.a2);
+  A.t3 = gmp<double>(ws, td.a3);
+}
+
+// Filter multiplier F(|k|)/N for the packed x-FFT.
+__device__ __forceinline__ cpx<double> filt_mul(gptr<const double> fx, int N, int n,
+                                                cpx<double> v) {
+  const int k = n <= (N >> 1) ? n : N - n;
+  const double f = fx[k] / (double)N;
+  return {v.re * f, v.im * f};
+}
+
+template <int NZ>
+__global__ void __launch_bounds__(256) k_rk_pre(const TankDesc* __restrict__ descs,
+                                                const int32_t* __restrict__ ids, char* ws,
+                                                RkCoef cf, const double* u, const double* w,
+                                                double* eta, double* Keta, RkBufs rb, int fftb) {
+  const TankDesc& td = descs[ids[blockIdx.x]];
+  const int nx = td.nx;
+  if (td.nz != NZ || nx < 8 || nx > 2048) return;
+  const gptr<const double> u0 = as_global(u + td.off2d);
+  const gptr<const double> w0 = as_global(w + td.off2d);
+  const gptr<double> e = as_global(eta + td.off1d);
+  const gptr<double> ke = as_global(Keta + td.off1d);
+  const gptr<double> eo = as_global(rb.eo + td.off1d);
+  const gptr<double> et = as_global(rb.etat + td.off1d);
+  const gptr<double> ex = as_global(rb.etax + td.off1d);
+  const gptr<const cpx<double>> tw = gcp<cpx<double>>(ws, td.tw[0]);
+  const gptr<const double> fx = gcp<double>(ws, td.filtx);
+  dx_rows<double>(1, nx, td.log2nx, td.kfac, tw, fftb, [=](int, int i) { return e[i]; },
+                  [=](int, int i, double v) { ex[i] = v; });
+  for (int i = tid(); i < nx; i += nthr()) {
+    const double rate = -u0[i] * ex[i] + w0[i];
+    et[i] = rate;
+    const double k = cf.a * ke[i] + cf.dt * rate;
+    ke[i] = k;
+    eo[i] = e[i];
+    e[i] = e[i] + cf.b * k;
+  }
+  __syncthreads();
+  spectral_rows<double>(1, nx, td.log2nx, tw, fftb, [=](int, int i) { return e[i]; },
+                        [=](int n, cpx<double> v) { return filt_mul(fx, nx, n, v); },
+                        [=](int, int i, double v) { e[i] = v; });
+}
+
+template <int NZ>
+__global__ void __launch_bounds__(256) k_rk_force(const TankDesc* __restrict__ descs,
+                                                  const int32_t* __restrict__ ids, char* ws,
+                                                  RkCoef cf, const double* u, const double* w,
+                                                  const double* Ku, const double* Kw, RkBufs rb,
+                                                  int fftb) {
+  const TankDesc& td = descs[ids[blockIdx.x]];
+  const int nx = td.nx, n = nx * NZ;
+  if (td.nz != NZ || nx < 8 || nx > 2048) return;
+  Ctx<double> c;
+  Lev<double> A;
+  rk_ctx(ws, td, fftb, c, A);
+  Ctx<double> cold = c;               // Div^old Grad^old for the viscous term
+  cold.g.an = c.g.ao;
+  cold.g.bn = c.g.bo;
+  cold.g.idn = c.g.ido;
+  const Geo<double> g = c.g;
+  const gptr<const double> sig = A.sig;
+  const gptr<const double> uu = as_global(u + td.off2d), wwp = as_global(w + td.off2d);
+  const gptr<const double> ku = as_global(Ku + td.off2d), kw = as_global(Kw + td.off2d);
+  const gptr<double> Fu = as_global(rb.Fu + td.off2d), Fw = as_global(rb.Fw + td.off2d);
+  const gptr<double> us = as_global(rb.us + td.off2d), wsv = as_global(rb.ws + td.off2d);
+  const gptr<double> b = as_global(rb.b + td.off2d);
+  const gptr<const double> et = as_global(rb.etat + td.off1d);
+  const gptr<const double> ex = as_global(rb.etax + td.off1d);
+  const gptr<double> t1 = A.t1, t2 = A.t2, t3 = A.t3;
+  const gptr<double> none(nullptr);
+  for (int comp = 0; comp < 2; ++comp) {
+    const gptr<const double> f = comp == 0 ? uu : wwp;
+    const gptr<double> F = comp == 0 ? Fu : Fw;
+    // F <- Div^old Grad^old f; leaves t1 = D_s f, t2 = D_x f
+    op_apply<double, NZ>(cold, A, FIN_FULL, f, F, gptr<const double>(nullptr), none, 0.0);
+    const gptr<const double> K = comp == 0 ? ku : kw;
+    const gptr<double> star = comp == 0 ? us : wsv;
+    for (int e = tid(); e < n; e += nthr()) {
+      const int j = e / nx, i = e - j * nx;
+      const double sx = g.ao[i] + g.bo[i] * sig[j];
+      const double wsig = -sig[j] * et[i] * g.ido[i] + uu[e] * sx + wwp[e] * g.ido[i];
+      double fo = -uu[e] * t2[e] - wsig * t1[e] + cf.nu * F[e];
+      if (comp == 0) fo -= cf.g * ex[i];
+      F[e] = fo;
+      star[e] = f[e] + cf.b * (cf.a * K[e] + cf.dt * fo);
+    }
+    __syncthreads();
+  }
+  // right-hand side: scale * Div^new(u*, w*) with the boundary rows
+  col_dsig<double, NZ>(nx, A.Ds, us, t1);
+  col_dsig<double, NZ>(nx, A.Ds, wsv, t3);
+  __syncthreads();
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb, [=](int j, int i) { return us[j * nx + i]; },
+                  [=](int j, int i, double v) { t2[j * nx + i] = v; });
+  const double scale = cf.rho / (cf.b * cf.dt);
+  for (int e = tid(); e < n; e += nthr()) {
+    const int j = e / nx, i = e - j * nx;
+    double v;
+    if (j == 0) v = 0.0;
+    else if (j == NZ - 1) v = -scale * (g.hx[i] * us[e] + wsv[e]);
+    else v = scale * (t2[e] + (g.an[i] + g.bn[i] * sig[j]) * t1[e] + g.idn[i] * t3[e]);
+    b[e] = v;
+  }
+}
+
+template <int NZ>
+__global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ descs,
+                                                 const int32_t* __restrict__ ids, char* ws,
+                                                 RkCoef cf, const double* p, double* u, double* w,
+                                                 double* Ku, double* Kw, RkBufs rb, int fftb) {
+  const TankDesc& td = descs[ids[blockIdx.x]];
+  const int nx = td.nx, n = nx * NZ;
+  if (td.nz != NZ || nx < 8 || nx > 2048) return;
+  Ctx<double> c;
+  Lev<double> A;
+  rk_ctx(ws, td, fftb, c, A);
+  const Geo<double> g = c.g;
+  const gptr<const double> sig = A.sig;
+  const gptr<const double> pp = as_global(p + td.off2d);
+  const gptr<double> uu = as_global(u + td.off2d), wwp = as_global(w + td.off2d);
+  const gptr<double> ku = as_global(Ku + td.off2d), kw = as_global(Kw + td.off2d);
+  const gptr<const double> Fu = as_global(rb.Fu + td.off2d), Fw = as_global(rb.Fw + td.off2d);
+  const gptr<double> r1 = as_global(rb.r1 + td.off2d), r2 = as_global(rb.r2 + td.off2d);
+  const gptr<double> t1 = A.t1, t2 = A.t2, t3 = A.t3;
+  const gptr<const double> fx = gcp<double>(ws, td.filtx);
+  const gptr<const double> fz = gcp<double>(ws, td.filtz);
+  col_dsig<double, NZ>(nx, A.Ds, pp, t1);
+  __syncthreads();
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb, [=](int j, int i) { return pp[j * nx + i]; },
+                  [=](int j, int i, double v) { t2[j * nx + i] = v; });
+  const double ir = 1.0 / cf.rho;
+  for (int e = tid(); e < n; e += nthr()) {
+    const int j = e / nx, i = e - j * nx;
+    const double gx = t2[e] + (g.ao[i] + g.bo[i] * sig[j]) * t1[e];
+    const double gz = t1[e] * g.ido[i];
+    const double a = cf.a * ku[e] + cf.dt * (Fu[e] - gx * ir);
+    const double bb = cf.a * kw[e] + cf.dt * (Fw[e] - gz * ir);
+    ku[e] = a;
+    kw[e] = bb;
+    r1[e] = uu[e] + cf.b * a;
+    r2[e] = wwp[e] + cf.b * bb;
+  }
+  __syncthreads();
+  for (int comp = 0; comp < 2; ++comp) {
+    const gptr<const double> src = comp == 0 ? gptr<const double>(r1) : gptr<const double>(r2);
+    const gptr<double> dst = comp == 0 ? uu : wwp;
+    spectral_rows<double>(NZ, nx, c.log2nx, c.tw, fftb,
+                          [=](int j, int i) { return src[j * nx + i]; },
+                          [=](int k, cpx<double> v) { return filt_mul(fx, nx, k, v); },
+                          [=](int j, int i, double v) { t3[j * nx + i] = v; });
+    col_dsig<double, NZ>(nx, fz, t3, dst);
+    __syncthreads();
+  }
+}
+
 }  // namespace pmgw

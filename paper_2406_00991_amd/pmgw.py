@@ -9,6 +9,8 @@ import ctypes
 import os
 import warnings
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmgw.so")
 
@@ -73,6 +75,8 @@ def lib():
         L.pmgw_plan_destroy.argtypes = [_vp]
         L.pmgw_plan_destroy.restype = None
         L.pmgw_last_error.restype = ctypes.c_char_p
+        L.pmgw_profile.argtypes = [_vp, ctypes.c_int32]
+        L.pmgw_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), _dp, _dp]
         _lib = L
     return _lib
 
@@ -245,3 +249,48 @@ def poisson_solve(plan, b, p, rtol=1e-10, maxit=100, sync=True, info_dev=None):
         warnings.warn("poisson_solve: a tank did not converge: " +
                       lib().pmgw_last_error().decode())
     return out
+
+
+def rk4_stage(plan, k, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10, maxit=100, info_dev=None):
+    """One stage k (1..5) of the low-storage RK scheme with the pressure projection, in place."""
+    import torch
+    f64 = torch.float64
+    dptr = _ptr(info_dev) if info_dev is not None else None
+    _check(lib().rk4_stage(plan._h, int(k), float(dt), _ptr(h, f64), _ptr(u, f64), _ptr(w, f64),
+                           _ptr(eta, f64), _ptr(Ku, f64), _ptr(Kw, f64), _ptr(Keta, f64),
+                           _ptr(p, f64), float(rtol), int(maxit), dptr))
+    _trace("rk4_stage")
+
+
+def rk4_step(plan, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10, maxit=100, info_dev=None):
+    """One full time step: stages 1..5 (stage 1 multiplies the registers K by zero)."""
+    for k in range(1, 6):
+        rk4_stage(plan, k, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol, maxit, info_dev)
+
+
+def profile_start(plan, capacity):
+    """Record event-pair timings of the next `capacity` solve-kernel launches of the plan."""
+    _check(lib().pmgw_profile(plan._h, int(capacity)))
+
+
+def profile_read(plan):
+    """(launches, total_ms, max_ms) of the recorded solve launches (synchronises)."""
+    n = ctypes.c_int32()
+    tot = ctypes.c_double()
+    mx = ctypes.c_double()
+    _check(lib().pmgw_profile_read(plan._h, ctypes.byref(n), ctypes.byref(tot), ctypes.byref(mx)))
+    return n.value, tot.value, mx.value
+
+
+def info_buffer(ntanks, device=None):
+    """Device array of ntanks pmgw_info records (16 bytes each) for the info_dev arguments."""
+    import torch
+    return torch.zeros(ntanks * 2, dtype=torch.float64, device=device or "cuda")
+
+
+def read_info(buf):
+    """Synchronously read an info_buffer: list of dicts (iters, status, relres) per tank."""
+    import torch
+    raw = buf.cpu().numpy().view(np.int32).reshape(-1, 4)
+    rel = buf.cpu().numpy().reshape(-1, 2)[:, 1]
+    return [dict(iters=int(r[0]), status=int(r[1]), relres=float(x)) for r, x in zip(raw, rel)]

@@ -1,0 +1,197 @@
+"""GPU parity of the time-stepping stage (rk4_stage through the C ABI) against the CPU oracle.
+
+The oracle's stage (Sec. 3.1-3.3, 3.6) runs on the same seeded initial state with its own
+pressure solve (dense LU for small grids; p-multigrid FGMRES at 5e-12 for the 256 x 17 wave,
+above that grid's rounding floor of ~4e-13).
+Both sides stop their solves at relative residuals far below the tolerances used here, so the
+differences left are solver-tolerance and rounding effects amplified by dt/rho (velocities) and
+the stage coefficients. Tolerances, relative to each field's max norm:
+- eta (set before the solve, only the kinematic update and the x-filter): 1e-12;
+- u, w, K_u, K_w: 1e-9; p: 1e-8 (the solves stop at 1e-12 .. 1e-13 relative residual and the
+  operator's condition number is ~1e4 at these sizes).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import krylov
+from oracle import lserk
+from oracle import operator as op
+from oracle import pmg
+from oracle import spectral as sp
+from paper_2406_00991_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class GpuTanks:
+    """Packed device state of a batch of tanks and the stage driver."""
+
+    def __init__(self, tanks, precision="fp64", **optkw):
+        from paper_2406_00991_amd import pmgw
+        torch = _torch()
+        self.pmgw = pmgw
+        self.tanks = tanks
+        opts = pmgw.default_opts(**optkw)
+        self.plan = pmgw.Plan([t["nx"] for t in tanks], [t["nz"] for t in tanks],
+                              [t["L"] for t in tanks], precision=precision, opts=opts)
+        dev = lambda arrs: torch.tensor(np.concatenate([np.asarray(a).ravel() for a in arrs]),
+                                        dtype=torch.float64, device="cuda")
+        self.h = dev([t["h"] for t in tanks])
+        self.u = dev([t["u"] for t in tanks])
+        self.w = dev([t["w"] for t in tanks])
+        self.eta = dev([t["eta"] for t in tanks])
+        self.Ku = torch.zeros_like(self.u)
+        self.Kw = torch.zeros_like(self.u)
+        self.Keta = torch.zeros_like(self.eta)
+        self.p = torch.zeros_like(self.u)
+        self.info = pmgw.info_buffer(len(tanks))
+
+    def stage(self, k, dt, rtol=1e-12, maxit=200):
+        self.pmgw.rk4_stage(self.plan, k, dt, self.h, self.u, self.w, self.eta, self.Ku, self.Kw,
+                            self.Keta, self.p, rtol=rtol, maxit=maxit, info_dev=self.info)
+
+    def infos(self):
+        return self.pmgw.read_info(self.info)
+
+    def fields(self, t):
+        """(u, w, eta, Ku, Kw, Keta, p) of tank t as numpy arrays."""
+        out2 = [self.plan.split2d(a)[t].cpu().numpy() for a in (self.u, self.w, self.Ku, self.Kw, self.p)]
+        out1 = [self.plan.split1d(a)[t].cpu().numpy() for a in (self.eta, self.Keta)]
+        u, w, Ku, Kw, p = out2
+        eta, Keta = out1
+        return dict(u=u, w=w, eta=eta, Ku=Ku, Kw=Kw, Keta=Keta, p=p)
+
+
+def fgmres_solver(rtol):
+    def solve(b, g_old, g_new, p0):
+        M = b.shape[0] - 1
+        H = pmg.Hierarchy(b.shape[1], M, g_old, g_new, pmg.PmgOptions())
+        x, info = krylov.fgmres(lambda v: op.apply(v, g_old, g_new), b, H, x0=p0, rtol=rtol,
+                                restart=30, maxit=300)
+        assert info["converged"]
+        return x
+    return solve
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def compare(got, s, tol_eta=1e-12, tol_uw=1e-9, tol_p=1e-8):
+    assert relerr(got["eta"], s.eta) <= tol_eta
+    assert relerr(got["Keta"], s.Keta) <= tol_eta
+    for key in ("u", "w", "Ku", "Kw"):
+        assert relerr(got[key], getattr(s, key)) <= tol_uw, key
+    assert relerr(got["p"], s.p) <= tol_p
+
+
+def sloped(wv, amp=0.05):
+    t = dict(wv)
+    t["h"] = wv["h"] + amp * np.sin(sp.x_nodes(wv["nx"], wv["L"]))
+    return t
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_stage_parity_small(precision):
+    """Five stages (one step) on a 32 x 9 Stokes wave over a sloped bed; every stage is compared."""
+    t = sloped(wl.stokes_wave(32, 9))
+    G = GpuTanks([t], precision)
+    s = lserk.State.rest_registers(t["u"], t["w"], t["eta"])
+    for k in range(1, 6):
+        G.stage(k, t["dt"])
+        lserk.stage(k, t["dt"], t["h"], t["L"], s, lserk.dense_solver)
+        assert G.infos()[0]["status"] == 0
+        compare(G.fields(0), s)
+
+
+def test_stage_parity_batched_uneven():
+    """Three tanks of different sizes in one plan advance one step; each matches its own oracle."""
+    tanks = [sloped(wl.stokes_wave(32, 9)), wl.stokes_wave(64, 17, steep=0.03),
+             sloped(wl.stokes_wave(16, 5, steep=0.02), 0.02)]
+    G = GpuTanks(tanks, "mixed")
+    states = [lserk.State.rest_registers(t["u"], t["w"], t["eta"]) for t in tanks]
+    dt = min(t["dt"] for t in tanks)
+    for k in range(1, 6):
+        G.stage(k, dt)
+        for t, s in zip(tanks, states):
+            lserk.stage(k, dt, t["h"], t["L"], s, lserk.dense_solver)
+    for i, s in enumerate(states):
+        compare(G.fields(i), s)
+
+
+def test_stage_parity_full_size_stokes():
+    """The 256 x 17 Stokes wave over one step, mixed precision, against the oracle's p-multigrid
+    FGMRES solve; both stop at 5e-12 relative residual."""
+    t = wl.stokes_wave(256, 17)
+    G = GpuTanks([t], "mixed")
+    s = lserk.State.rest_registers(t["u"], t["w"], t["eta"])
+    solve = fgmres_solver(5e-12)
+    for k in range(1, 6):
+        G.stage(k, t["dt"], rtol=5e-12)
+        lserk.stage(k, t["dt"], t["h"], t["L"], s, solve)
+    compare(G.fields(0), s)
+
+
+def test_still_water_stays_at_rest():
+    nx, nz, L = 16, 9, 2 * math.pi
+    h = 1.0 + 0.1 * np.cos(sp.x_nodes(nx, L))
+    z = np.zeros((nz, nx))
+    t = dict(nx=nx, nz=nz, L=L, h=h, u=z, w=z, eta=np.zeros(nx))
+    G = GpuTanks([t])
+    for k in range(1, 6):
+        G.stage(k, 0.05)
+    f = G.fields(0)
+    for key in ("u", "w", "eta", "p", "Ku", "Kw", "Keta"):
+        assert np.abs(f[key]).max() == 0.0, key
+
+
+def test_divergence_free_and_mass_conserved():
+    """After each step the velocity is (to the filter and solver tolerance) divergence free under
+    the new surface, the bed is impermeable and the mean surface elevation is unchanged."""
+    t = sloped(wl.stokes_wave(64, 17))
+    G = GpuTanks([t], "mixed")
+    mass0 = t["eta"].sum()
+    for _ in range(3):
+        for k in range(1, 6):
+            G.stage(k, t["dt"])
+    f = G.fields(0)
+    g_new = op.Geometry(t["h"], f["eta"], t["L"])
+    M = t["nz"] - 1
+    div = op.div(f["u"], f["w"], g_new, M)[1:M]
+    scale = np.abs(sp.dx(f["u"], t["L"])).max()
+    assert np.abs(div).max() < 1e-8 * scale     # the oracle's own run gives ~2e-10 here
+    assert abs(f["eta"].sum() - mass0) < 1e-10 * t["nx"] * np.abs(t["eta"]).max()
+
+
+def test_linear_wave_phase_speed():
+    """A small-amplitude wave after a quarter period matches linear theory, a sin(kx)."""
+    wv = wl.airy_wave(16, 9)
+    T = 0.25 * wv["period"]
+    n = int(math.ceil(T / wv["dt"]))
+    dt = T / n
+    G = GpuTanks([wv])
+    for _ in range(n):
+        for k in range(1, 6):
+            G.stage(k, dt)
+    x = sp.x_nodes(16, wv["L"])
+    exact = wv["amp"] * np.cos(wv["k"] * x - wv["omega"] * T)
+    assert np.abs(G.fields(0)["eta"] - exact).max() / wv["amp"] < 2e-3
+
+
+def test_stage_argument_errors():
+    from paper_2406_00991_amd import pmgw
+    t = wl.stokes_wave(16, 5)
+    G = GpuTanks([t])
+    with pytest.raises(pmgw.PmgwError):
+        G.stage(0, t["dt"])
+    with pytest.raises(pmgw.PmgwError):
+        G.stage(6, t["dt"])
+    with pytest.raises(pmgw.PmgwError):
+        G.stage(1, -1.0)
