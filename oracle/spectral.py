@@ -39,12 +39,14 @@ def dx(f, L):
     """First x-derivative along the last axis: F^-1(i kappa F(f)), Nyquist zeroed (Sec. 3.5).
 
     The multiplier is odd in k, so the operator is real: real input gives real output, and a
-    complex input is differentiated component-wise (needed by the complex-step checks).
+    complex input is differentiated part by part (real and imaginary separately), so that the
+    rounding of one part never leaks into the other (complex-step derivatives rely on that).
     """
     f = np.asarray(f)
+    if np.iscomplexobj(f):
+        return dx(f.real, L) + 1j * dx(f.imag, L)
     nx = f.shape[-1]
-    out = np.fft.ifft(1j * wavenumbers(nx, L) * np.fft.fft(f, axis=-1), axis=-1)
-    return out.real if np.isrealobj(f) else out
+    return np.fft.ifft(1j * wavenumbers(nx, L) * np.fft.fft(f, axis=-1), axis=-1).real
 
 
 def dxx_spectral(f, L):
@@ -77,14 +79,16 @@ def filter_x(f, L, frac=0.5, alpha=36.0, s=2.0):
 
     Mode index i = |k|, N = nx/2, N_c = floor(frac * N): factor 1 for i <= N_c and
     exp(-alpha ((i - N_c)/(N + 1 - N_c))^s) above. (The exponent's sign is printed positive; a
-    filter must damp, so the oracle uses the negative sign.)
+    filter must damp, so the oracle uses the negative sign.) Complex input is filtered part by
+    part, as in ``dx``.
     """
     f = np.asarray(f)
+    if np.iscomplexobj(f):
+        return filter_x(f.real, L, frac, alpha, s) + 1j * filter_x(f.imag, L, frac, alpha, s)
     nx = f.shape[-1]
     i = np.abs(np.fft.fftfreq(nx, d=1.0 / nx))
     sig = filter_factors(nx // 2, int(np.floor(frac * (nx // 2))), alpha, s, i)
-    out = np.fft.ifft(sig * np.fft.fft(f, axis=-1), axis=-1)
-    return out.real if np.isrealobj(f) else out
+    return np.fft.ifft(sig * np.fft.fft(f, axis=-1), axis=-1).real
 
 
 def filter_factors(N, Nc, alpha, s, i):
