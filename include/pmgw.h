@@ -156,12 +156,27 @@ int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, 
               int32_t maxit, pmgw_info* info_dev);
 
 /*
- * lambda = A^-T g: solve the transposed system of the geometry last set (FGMRES on the
- * transposed operator, float64, right-preconditioned by the forward V-cycle). lambda holds
- * the initial guess on entry. Same conventions as poisson_solve.
+ * out = A^T lambda for the operator of laplacian_apply (its exact transpose: D_x^T = -D_x,
+ * explicit D_sigma^T, transposed boundary rows). Needed by the discrete adjoint of the
+ * pressure solve. lambda and out are device fields and must not overlap. Always float64.
+ */
+int pmgw_adjoint_apply(pmgw_plan plan, const double* lambda, double* out);
+
+/*
+ * z = M^T r, the transpose of the linear map r -> pmg_vcycle(r): the V-cycle on A^T with
+ * every smoothing step transposed and taken in reverse order, restriction by P^T and
+ * prolongation by R^T. In PMGW_FP64 plans <pmg_vcycle(a), b> = <a, pmgw_adjoint_vcycle(b)> to
+ * rounding. r and z must not overlap.
+ */
+int pmgw_adjoint_vcycle(pmgw_plan plan, const double* r, double* z);
+
+/*
+ * lambda = A^-T g: flexible GMRES on the transposed operator, right-preconditioned by M^T
+ * (pmgw_adjoint_vcycle), in float64 (the cycle in the plan's precision). lambda holds the
+ * initial guess on entry. Same conventions, stopping rule and return values as poisson_solve.
  */
 int pmgw_adjoint_solve(pmgw_plan plan, const double* g, double* lambda, double rtol,
-                       int32_t maxit, pmgw_info* info_host);
+                       int32_t maxit, pmgw_info* info_host, pmgw_info* info_dev);
 
 /* Release the plan (not the workspace, which the caller owns). NULL is ignored. */
 void pmgw_plan_destroy(pmgw_plan plan);

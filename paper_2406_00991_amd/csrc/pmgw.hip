@@ -68,6 +68,14 @@ double cheb_T(int m, double theta) { return std::cos(m * theta); }
 
 // Restriction fine order Mf -> Mc = Mf/2: nodal values -> Chebyshev coefficients, keep m <= Mc,
 // evaluate at the coarse nodes; surface and bed rows are injected. [(Mc+1)][(Mf+1)].
+// B = A^T for a row-major rows x cols matrix A.
+std::vector<double> transpose(const std::vector<double>& A, int rows, int cols) {
+  std::vector<double> B((size_t)rows * cols);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) B[(size_t)c * rows + r] = A[(size_t)r * cols + c];
+  return B;
+}
+
 std::vector<double> restriction(int Mf) {
   const int Mc = Mf / 2, nf = Mf + 1, nc = Mc + 1;
   std::vector<double> R(nc * nf, 0.0);
@@ -216,7 +224,7 @@ int nz_class(int nz) { return nz == 3 ? 0 : nz == 5 ? 1 : nz == 9 ? 2 : nz == 17
 // Largest workgroup the solve kernel is compiled for (its register budget follows from it).
 constexpr int kSolveMaxThreads = 256;
 
-template <typename TV, int NZ>
+template <typename TV, int NZ, bool TR>
 void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, double rtol,
                   int maxit, pmgw_info_dev* info, const KOpts& o) {
   const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
@@ -226,29 +234,33 @@ void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, d
   const int thr = p->opts.threads ? p->opts.threads : MAXT;
   // Two halves of 32 KB of FFT LDS per workgroup: two workgroups fit on one CU.
   const int fftb = 32768;
-  hipLaunchKernelGGL((k_solve<TV, NZ, MAXT>), dim3((unsigned)nt), dim3(thr), (size_t)(2 * fftb),
+  hipLaunchKernelGGL((k_solve<TV, NZ, MAXT, TR>), dim3((unsigned)nt), dim3(thr), (size_t)(2 * fftb),
                      p->stream, d, ids, p->ws, mode, in, out, rtol, maxit, info, o, fftb);
 }
 
-template <typename TV>
+template <typename TV, bool TR>
 void launch_all(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
                 pmgw_info_dev* info, const KOpts& o) {
-  if (!p->ids[0].empty()) launch_class<TV, 3>(p, 0, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[1].empty()) launch_class<TV, 5>(p, 1, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[2].empty()) launch_class<TV, 9>(p, 2, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[3].empty()) launch_class<TV, 17>(p, 3, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[4].empty()) launch_class<TV, 33>(p, 4, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[0].empty()) launch_class<TV, 3, TR>(p, 0, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[1].empty()) launch_class<TV, 5, TR>(p, 1, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[2].empty()) launch_class<TV, 9, TR>(p, 2, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[3].empty()) launch_class<TV, 17, TR>(p, 3, mode, in, out, rtol, maxit, info, o);
+  if (!p->ids[4].empty()) launch_class<TV, 33, TR>(p, 4, mode, in, out, rtol, maxit, info, o);
 }
 
+// tr: the transposed operator and cycle (adjoint solves).
 int launch_solve(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
-                 pmgw_info_dev* info) {
+                 pmgw_info_dev* info, bool tr = false) {
   const KOpts o = kopts(p);
-  const bool timed = p->prof_on && mode == MODE_SOLVE && p->prof_n < (int)p->ev0.size();
+  const bool timed = p->prof_on && mode == MODE_SOLVE && !tr && p->prof_n < (int)p->ev0.size();
   if (timed) (void)hipEventRecord(p->ev0[p->prof_n], p->stream);
-  if (p->prec == PMGW_FP64)
-    launch_all<double>(p, mode, in, out, rtol, maxit, info, o);
-  else
-    launch_all<float>(p, mode, in, out, rtol, maxit, info, o);
+  if (p->prec == PMGW_FP64) {
+    if (tr) launch_all<double, true>(p, mode, in, out, rtol, maxit, info, o);
+    else launch_all<double, false>(p, mode, in, out, rtol, maxit, info, o);
+  } else {
+    if (tr) launch_all<float, true>(p, mode, in, out, rtol, maxit, info, o);
+    else launch_all<float, false>(p, mode, in, out, rtol, maxit, info, o);
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "solve kernel launch");
   if (timed) (void)hipEventRecord(p->ev1[p->prof_n++], p->stream);
@@ -381,6 +393,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
         if (lv.nzc) {
           lv.R[pr] = cur; cur = align256(cur + w * lv.nzc * lv.nz);
           lv.P[pr] = cur; cur = align256(cur + w * lv.nz * lv.nzc);
+          lv.PT[pr] = cur; cur = align256(cur + w * lv.nzc * lv.nz);
+          lv.RT[pr] = cur; cur = align256(cur + w * lv.nz * lv.nzc);
         }
       }
       ++l;
@@ -466,6 +480,12 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
         put<float>(p->image, lv.R[1], R);
         put<double>(p->image, lv.P[0], P);
         put<float>(p->image, lv.P[1], P);
+        const auto PT = transpose(P, lv.nz, lv.nzc);
+        const auto RT = transpose(R, lv.nzc, lv.nz);
+        put<double>(p->image, lv.PT[0], PT);
+        put<float>(p->image, lv.PT[1], PT);
+        put<double>(p->image, lv.RT[0], RT);
+        put<float>(p->image, lv.RT[1], RT);
       }
     }
     std::vector<double> tw(2 * d.nx);
@@ -554,9 +574,12 @@ int pmg_vcycle(pmgw_plan p, const double* r, double* z) {
   return launch_solve(p, MODE_VCYCLE, r, z, 0.0, 0, nullptr);
 }
 
-int poisson_solve(pmgw_plan p, const double* b, double* x, double rtol, int32_t maxit,
-                  pmgw_info* info_host, pmgw_info* info_dev) {
-  g_err.clear();
+}  // extern "C"
+
+namespace {
+
+int solve_entry(pmgw_plan p, bool tr, const double* b, double* x, double rtol, int32_t maxit,
+                pmgw_info* info_host, pmgw_info* info_dev) {
   int rc = check_plan(p);
   if (rc) return rc;
   if (!p->geometry_set) return fail(PMGW_EINVAL, "geometry not set");
@@ -566,7 +589,7 @@ int poisson_solve(pmgw_plan p, const double* b, double* x, double rtol, int32_t 
   if (maxit < 1) return fail(PMGW_EINVAL, "maxit must be >= 1");
   pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev)
                                   : reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
-  rc = launch_solve(p, MODE_SOLVE, b, x, rtol, maxit, dinfo);
+  rc = launch_solve(p, MODE_SOLVE, b, x, rtol, maxit, dinfo, tr);
   if (rc) return rc;
   if (info_host) {
     hipError_t e = hipMemcpyAsync(info_host, dinfo, sizeof(pmgw_info) * p->ntanks,
@@ -585,6 +608,42 @@ int poisson_solve(pmgw_plan p, const double* b, double* x, double rtol, int32_t 
     return worst;
   }
   return PMGW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int poisson_solve(pmgw_plan p, const double* b, double* x, double rtol, int32_t maxit,
+                  pmgw_info* info_host, pmgw_info* info_dev) {
+  g_err.clear();
+  return solve_entry(p, false, b, x, rtol, maxit, info_host, info_dev);
+}
+
+int pmgw_adjoint_apply(pmgw_plan p, const double* lam, double* out) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!p->geometry_set) return fail(PMGW_EINVAL, "geometry not set");
+  if (!lam || !out) return fail(PMGW_EINVAL, "lambda and out must be non-NULL");
+  if (lam == out) return fail(PMGW_EINVAL, "lambda and out must not overlap");
+  return launch_solve(p, MODE_APPLY, lam, out, 0.0, 0, nullptr, true);
+}
+
+int pmgw_adjoint_vcycle(pmgw_plan p, const double* r, double* z) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!p->geometry_set) return fail(PMGW_EINVAL, "geometry not set");
+  if (!r || !z) return fail(PMGW_EINVAL, "r and z must be non-NULL");
+  if (r == z) return fail(PMGW_EINVAL, "r and z must not overlap");
+  return launch_solve(p, MODE_VCYCLE, r, z, 0.0, 0, nullptr, true);
+}
+
+int pmgw_adjoint_solve(pmgw_plan p, const double* g, double* lam, double rtol, int32_t maxit,
+                       pmgw_info* info_host, pmgw_info* info_dev) {
+  g_err.clear();
+  return solve_entry(p, true, g, lam, rtol, maxit, info_host, info_dev);
 }
 
 void pmgw_plan_destroy(pmgw_plan p) { delete p; }
@@ -698,8 +757,3 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   return launch_rk_all(p, 2, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
 }
 
-extern "C" int pmgw_adjoint_solve(pmgw_plan p, const double*, double*, double, int32_t,
-                                  pmgw_info*) {
-  (void)p;
-  return fail(PMGW_EINVAL, "pmgw_adjoint_solve is not available in this build");
-}

@@ -438,7 +438,9 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, gptr<const cp
 // Flat-mode line solve in Fourier space: for each mode k in [0, N/2], unpack the spectra of
 // the nz real rows from the packed pairs, multiply by the inverse mode block (real, the same
 // for k and N-k), repack, and fold in the 1/N of the inverse FFT. minv is [NZ][NZ][N/2+1].
-template <typename T, int NZ>
+// TR: use the transposed blocks (the transpose of the whole real map, because the block of
+// mode k equals that of mode N-k).
+template <typename T, int NZ, bool TR = false>
 __device__ void mode_matvec(int N, gptr<const T> __restrict__ minv, gptr<cpx<T>> spec) {
   constexpr int NP = (NZ + 1) / 2;
   const int nh = (N >> 1) + 1;
@@ -458,11 +460,11 @@ __device__ void mode_matvec(int N, gptr<const T> __restrict__ minv, gptr<cpx<T>>
       const int j0 = 2 * p, j1 = 2 * p + 1;
 #pragma unroll
       for (int l = 0; l < NZ; ++l) {
-        const T a = minv[(j0 * NZ + l) * nh + k];
+        const T a = minv[(TR ? l * NZ + j0 : j0 * NZ + l) * nh + k];
         s0.re += a * rh[l].re;
         s0.im += a * rh[l].im;
         if (j1 < NZ) {
-          const T c = minv[(j1 * NZ + l) * nh + k];
+          const T c = minv[(TR ? l * NZ + j1 : j1 * NZ + l) * nh + k];
           s1.re += c * rh[l].re;
           s1.im += c * rh[l].im;
         }
@@ -485,6 +487,7 @@ template <typename T>
 struct Lev {
   int nz, nzc;
   gptr<const T> Ds, sig, colinv, modeinv, R, P;
+  gptr<const T> PT, RT;          // P^T [nzc][nz] and R^T [nz][nzc] (transposed V-cycle)
   gptr<T> x, f, r, t1, t2, t3;
   gptr<cpx<T>> spec;
 };
@@ -511,7 +514,7 @@ __device__ __forceinline__ Lev<T> uni(const Lev<T>& L) {
   Lev<T> u;
   u.nz = uni(L.nz); u.nzc = uni(L.nzc);
   u.Ds = uni(L.Ds); u.sig = uni(L.sig); u.colinv = uni(L.colinv); u.modeinv = uni(L.modeinv);
-  u.R = uni(L.R); u.P = uni(L.P);
+  u.R = uni(L.R); u.P = uni(L.P); u.PT = uni(L.PT); u.RT = uni(L.RT);
   u.x = uni(L.x); u.f = uni(L.f); u.r = uni(L.r); u.t1 = uni(L.t1); u.t2 = uni(L.t2);
   u.t3 = uni(L.t3); u.spec = uni(L.spec);
   return u;
@@ -609,8 +612,8 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __res
   }
 }
 
-// x = omega B_i^-1 f_i (column step from a zero iterate: the residual is f).
-template <typename T, int NZ>
+// x = omega B_i^-1 f_i (column step from a zero iterate: the residual is f); TR: B_i^-T.
+template <typename T, int NZ, bool TR = false>
 __device__ void col_solve_zero(int nx, gptr<const T> __restrict__ cinv, gptr<const T> f,
                                gptr<T> x, T omega) {
   for (int i = tid(); i < nx; i += nthr()) {
@@ -621,7 +624,7 @@ __device__ void col_solve_zero(int nx, gptr<const T> __restrict__ cinv, gptr<con
     for (int j = 0; j < NZ; ++j) {
       T s = T(0);
 #pragma unroll
-      for (int l = 0; l < NZ; ++l) s += cinv[(j * NZ + l) * nx + i] * v[l];
+      for (int l = 0; l < NZ; ++l) s += cinv[(TR ? l * NZ + j : j * NZ + l) * nx + i] * v[l];
       x[j * nx + i] = omega * s;
     }
   }
@@ -695,6 +698,118 @@ __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int m
   __syncthreads();
 }
 
+// ----------------------------------------------------------------------------- transpose
+//
+// A^T lam for the operator above. With Li = lam on the interior rows (0 on rows 0 and M):
+//   Gbar_x = -D_x Li + D_s^T (sx_new Li) + e_M (-h_x lam_M)
+//   Gbar_z =           D_s^T (Li / d_new) + e_M (-lam_M)
+//   A^T lam = -D_x Gbar_x + D_s^T (sx_old Gbar_x + Gbar_z / d_old) + e_0 lam_0
+// (D_x is antisymmetric). Phases:
+//   A: t1 = D_s^T (sx_new Li) + bed part of Gbar_x,  t2 = Gbar_z      (column phase)
+//   B: t3 = D_x Li                                                   (row FFTs, mask on load)
+//   C: out = D_x Gbar_x with Gbar_x = t1 - t3 formed on load          (row FFTs)
+//   D: finish (column phase): mode FIN_APPLY writes A^T in, FIN_RESID f - A^T in, FIN_COLSTEP
+//      also applies x += omega B_i^-T (f - A^T in)_i (x may alias in; out must not).
+template <typename T, int NZ>
+__device__ void colT_start(int nx, gptr<const T> __restrict__ Ds, gptr<const T> __restrict__ sig,
+                           const Geo<T>& g, gptr<const T> in, gptr<T> t1, gptr<T> t2) {
+  for (int i = tid(); i < nx; i += nthr()) {
+    const T an = g.an[i], bn = g.bn[i], idn = g.idn[i], hx = g.hx[i];
+    T sl[NZ], il[NZ];
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) {
+      const T v = (l == 0 || l == NZ - 1) ? T(0) : in[l * nx + i];
+      sl[l] = (an + bn * sig[l]) * v;
+      il[l] = idn * v;
+    }
+    const T lamM = in[(NZ - 1) * nx + i];
+#pragma unroll 1
+    for (int j = 0; j < NZ; ++j) {
+      T s1 = T(0), s2 = T(0);
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) {
+        const T d = Ds[l * NZ + j];
+        s1 += d * sl[l];
+        s2 += d * il[l];
+      }
+      if (j == NZ - 1) {
+        s1 -= hx * lamM;
+        s2 -= lamM;
+      }
+      t1[j * nx + i] = s1;
+      t2[j * nx + i] = s2;
+    }
+  }
+}
+
+template <typename T, int NZ>
+__device__ __forceinline__ void colT_finish(int mode, int nx, gptr<const T> __restrict__ Ds,
+                                            gptr<const T> __restrict__ sig, const Geo<T>& g,
+                                            gptr<const T> in, gptr<const T> t1,
+                                            gptr<const T> t2, gptr<const T> t3, gptr<T> out,
+                                            gptr<const T> f, gptr<T> x,
+                                            gptr<const T> __restrict__ cinv, T omega) {
+  for (int i = tid(); i < nx; i += nthr()) {
+    const T ao = g.ao[i], bo = g.bo[i], ido = g.ido[i];
+    T v[NZ], o[NZ];
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) {
+      const T gbx = t1[l * nx + i] - t3[l * nx + i];
+      v[l] = (ao + bo * sig[l]) * gbx + ido * t2[l * nx + i];
+      o[l] = -out[l * nx + i];
+    }
+    o[0] += in[i];
+#pragma unroll 1
+    for (int j = 0; j < NZ; ++j) {
+      T s = o[j];
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) s += Ds[l * NZ + j] * v[l];
+      o[j] = (mode == FIN_APPLY) ? s : f[j * nx + i] - s;
+    }
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) out[l * nx + i] = o[l];
+    if (mode == FIN_COLSTEP) {
+#pragma unroll 1
+      for (int j = 0; j < NZ; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) s += cinv[(l * NZ + j) * nx + i] * o[l];
+        x[j * nx + i] += omega * s;
+      }
+    }
+  }
+}
+
+template <typename T, int NZ>
+__device__ __forceinline__ void op_apply_T(const Ctx<T>& c, const Lev<T>& L, int mode,
+                                           gptr<const T> in, gptr<T> out, gptr<const T> f,
+                                           gptr<T> x, T omega) {
+  const int nx = c.nx;
+  const gptr<T> t1 = L.t1;
+  const gptr<T> t2 = L.t2;
+  const gptr<T> t3 = L.t3;
+  const Geo<T> g = c.g;
+  colT_start<T, NZ>(nx, L.Ds, L.sig, g, in, t1, t2);
+  __syncthreads();
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
+             [=](int j, int i) { return (j == 0 || j == NZ - 1) ? T(0) : in[j * nx + i]; },
+             [=](int j, int i, T v) { t3[j * nx + i] = v; });
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
+             [=](int j, int i) { return t1[j * nx + i] - t3[j * nx + i]; },
+             [=](int j, int i, T v) { out[j * nx + i] = v; });
+  colT_finish<T, NZ>(mode, nx, L.Ds, L.sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega);
+  __syncthreads();
+}
+
+// Applies A (TR = false) or A^T (TR = true).
+template <typename T, int NZ, bool TR>
+__device__ __forceinline__ void op_any(const Ctx<T>& c, const Lev<T>& L, int mode,
+                                       gptr<const T> in, gptr<T> out, gptr<const T> f,
+                                       gptr<T> x, T omega) {
+  if constexpr (TR) op_apply_T<T, NZ>(c, L, mode, in, out, f, x, omega);
+  else op_apply<T, NZ>(c, L, mode, in, out, f, x, omega);
+}
+
 template <typename P>
 __device__ __forceinline__ void fill_zero(P p, int n) {
   for (int e = tid(); e < n; e += nthr()) p[e] = 0;
@@ -711,7 +826,12 @@ __device__ __forceinline__ void fill_zero(P p, int n) {
 // in the order nu1 x (COL, MODE), DOWN, nu2 x (COL, MODE); the coarsest level (3 rows) runs
 // coarse_pairs x (COL, MODE). The operator appears once in the loop body, which keeps each
 // level's code compact.
-template <typename T, int NZ, class LP>
+//
+// TR = true gives the transpose M^T of the cycle's linear map M (the preconditioner of the
+// adjoint solve): the same cycle on A^T with every step's order reversed (nu2 x (MODE, COL),
+// DOWN, nu1 x (MODE, COL)), transposed block inverses, restriction by P^T and prolongation by
+// R^T. (Reverse-mode differentiation of the cycle gives exactly this sequence.)
+template <typename T, int NZ, class LP, bool TR = false>
 __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   const Ctx<T> c = uni(c_);
   const LP lev = uni(lev_);
@@ -723,41 +843,48 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   const T wc = T(o.omega_c), wm = T(o.omega_m);
   const Lev<T> L = uni(lev(l));
   enum { COL = 0, MODE = 1, DOWN = 2 };
-  const int npre = (NZ == 3) ? o.coarse_pairs : o.nu1;
-  const int npost = (NZ == 3) ? 0 : o.nu2;
+  const int first = TR ? MODE : COL, second = TR ? COL : MODE;
+  const int npre = (NZ == 3) ? o.coarse_pairs : (TR ? o.nu2 : o.nu1);
+  const int npost = (NZ == 3) ? 0 : (TR ? o.nu1 : o.nu2);
   const int nops = 2 * npre + ((NZ == 3) ? 0 : 1) + 2 * npost;
   bool xzero = true;
   for (int q = 0; q < nops; ++q) {
     int kind;
-    if (q < 2 * npre) kind = (q & 1) ? MODE : COL;
+    if (q < 2 * npre) kind = (q & 1) ? second : first;
     else if (NZ != 3 && q == 2 * npre) kind = DOWN;
-    else kind = ((q - 2 * npre - 1) & 1) ? MODE : COL;
-    if (!(xzero && kind != MODE))
-      op_apply<T, NZ>(c, L, kind == COL ? FIN_COLSTEP : FIN_RESID, L.x, L.r, L.f, L.x, wc);
+    else kind = ((q - 2 * npre - 1) & 1) ? second : first;
+    if (!xzero)
+      op_any<T, NZ, TR>(c, L, kind == COL ? FIN_COLSTEP : FIN_RESID, L.x, L.r, L.f, L.x, wc);
     if (kind == COL) {
       if (xzero) {
-        col_solve_zero<T, NZ>(nx, L.colinv, L.f, L.x, wc);
+        col_solve_zero<T, NZ, TR>(nx, L.colinv, L.f, L.x, wc);
         __syncthreads();
         xzero = false;
       }
     } else if (kind == MODE) {
-      const gptr<const T> r = L.r;
+      const gptr<const T> r = xzero ? gptr<const T>(L.f) : gptr<const T>(L.r);
       rows_fft_to_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb,
                             [=](int j, int i) { return r[j * nx + i]; }, L.spec);
-      mode_matvec<T, NZ>(nx, L.modeinv, L.spec);
+      mode_matvec<T, NZ, TR>(nx, L.modeinv, L.spec);
       __syncthreads();
       const gptr<T> x = L.x;
-      rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb, L.spec,
-                               [=](int j, int i, T v) { x[j * nx + i] += wm * v; });
+      if (xzero)
+        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb, L.spec,
+                                 [=](int j, int i, T v) { x[j * nx + i] = wm * v; });
+      else
+        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb, L.spec,
+                                 [=](int j, int i, T v) { x[j * nx + i] += wm * v; });
+      xzero = false;
     } else {
       if constexpr (NZ > 3) {
         constexpr int NZC = (NZ + 1) / 2;
         const Lev<T> C = uni(lev(l + 1));
         if (xzero) fill_zero(L.x, NZ * nx);
-        col_restrict<T, NZ>(nx, L.R, xzero ? gptr<const T>(L.f) : gptr<const T>(L.r), C.f);
+        col_restrict<T, NZ>(nx, TR ? L.PT : L.R,
+                            xzero ? gptr<const T>(L.f) : gptr<const T>(L.r), C.f);
         __syncthreads();
-        vcycle<T, NZC>(c, lev, l + 1, o);
-        col_prolong_add<T, NZ>(nx, L.P, C.x, L.x);
+        vcycle<T, NZC, LP, TR>(c, lev, l + 1, o);
+        col_prolong_add<T, NZ>(nx, TR ? L.RT : L.P, C.x, L.x);
         __syncthreads();
         xzero = false;
       }

@@ -57,6 +57,7 @@ __device__ Lev<T> make_lev(char* ws, const LevelDesc& d) {
   L.nz = d.nz; L.nzc = d.nzc;
   L.Ds = gcp<T>(ws, d.ds[pr]); L.sig = gcp<T>(ws, d.sig[pr]);
   L.R = gcp<T>(ws, d.R[pr]); L.P = gcp<T>(ws, d.P[pr]);
+  L.PT = gcp<T>(ws, d.PT[pr]); L.RT = gcp<T>(ws, d.RT[pr]);
   L.colinv = gcp<T>(ws, d.colinv); L.modeinv = gcp<T>(ws, d.modeinv);
   L.x = gmp<T>(ws, d.x); L.f = gmp<T>(ws, d.f); L.r = gmp<T>(ws, d.r);
   L.t1 = gmp<T>(ws, d.t1); L.t2 = gmp<T>(ws, d.t2); L.t3 = gmp<T>(ws, d.t3);
@@ -296,7 +297,8 @@ struct KrylovLds {
 // ids[]. mode MODE_APPLY: out = A in. MODE_VCYCLE: out = V-cycle(in). MODE_SOLVE: FGMRES(restart)
 // on A out = in with out as initial guess (paper Sec. 4.4): right preconditioning by one V-cycle,
 // modified Gram-Schmidt, Givens rotations, stop on the true relative residual.
-template <typename TV, int NZ, int MAXT>
+// TR = true does the same with A^T and the transposed cycle M^T (the adjoint solve).
+template <typename TV, int NZ, int MAXT, bool TR = false>
 __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ descs,
                                                 const int32_t* __restrict__ ids, char* ws,
                                                 int mode, const double* in, double* out,
@@ -332,14 +334,14 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
   Lev<TV> L0 = levs(0);
 
   if (mode == MODE_APPLY) {
-    op_apply<double, NZ>(c64, A64, FIN_APPLY, as_global(b), as_global(x),
+    op_any<double, NZ, TR>(c64, A64, FIN_APPLY, as_global(b), as_global(x),
                          gptr<const double>(nullptr), gptr<double>(nullptr), 0.0);
     return;
   }
   if (mode == MODE_VCYCLE) {
     for (int e = tid(); e < n; e += nthr()) L0.f[e] = (TV)b[e];
     __syncthreads();
-    vcycle<TV, NZ>(cv, levs, 0, o);
+    vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
     for (int e = tid(); e < n; e += nthr()) x[e] = (double)L0.x[e];
     return;
   }
@@ -363,7 +365,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
   }
   const int m = min(o.restart, kMaxRestart);
   for (;;) {
-    op_apply<double, NZ>(c64, A64, FIN_RESID, as_global((const double*)x), as_global(V),
+    op_any<double, NZ, TR>(c64, A64, FIN_RESID, as_global((const double*)x), as_global(V),
                          as_global(b), gptr<double>(nullptr), 0.0);
     s = 0.0;
     for (int e = tid(); e < n; e += nthr()) s += V[e] * V[e];
@@ -387,16 +389,16 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
       if constexpr (std::is_same<TV, double>::value) {
         const LevSet<TV> lz{ws, &td, as_global(reinterpret_cast<TV*>(vj)),
                             as_global(reinterpret_cast<TV*>(zj))};
-        vcycle<TV, NZ>(cv, lz, 0, o);
+        vcycle<TV, NZ, LevSet<TV>, TR>(cv, lz, 0, o);
       } else {
         for (int e = tid(); e < n; e += nthr()) L0.f[e] = (TV)vj[e];
         __syncthreads();
-        vcycle<TV, NZ>(cv, levs, 0, o);
+        vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
         for (int e = tid(); e < n; e += nthr()) zj[e] = (double)L0.x[e];
         __syncthreads();
       }
       // w = A z_j
-      op_apply<double, NZ>(c64, A64, FIN_APPLY, as_global((const double*)zj), as_global(w),
+      op_any<double, NZ, TR>(c64, A64, FIN_APPLY, as_global((const double*)zj), as_global(w),
                            gptr<const double>(nullptr), gptr<double>(nullptr), 0.0);
       // modified Gram-Schmidt, each pass fuses the previous update with the next dot
       double hprev = 0.0;

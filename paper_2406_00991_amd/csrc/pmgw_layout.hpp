@@ -21,6 +21,8 @@ struct LevelDesc {
   int64_t sig[2];                   // sigma_j [nz]
   int64_t R[2];                     // restriction [nzc][nz]
   int64_t P[2];                     // prolongation [nz][nzc]
+  int64_t PT[2];                    // P^T [nzc][nz] (restriction of the transposed cycle)
+  int64_t RT[2];                    // R^T [nz][nzc] (prolongation of the transposed cycle)
   int64_t colinv;                   // inverse column blocks [nz][nz][nx] (V-cycle precision)
   int64_t modeinv;                  // inverse flat-mode blocks [nz][nz][nx/2+1]
   int64_t x, f, r, t1, t2, t3;      // level vectors [nz][nx] (V-cycle precision)

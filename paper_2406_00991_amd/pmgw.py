@@ -71,7 +71,9 @@ def lib():
         L.rk4_stage.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, _vp]
         L.pmgw_adjoint_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
-                                         ctypes.POINTER(Info)]
+                                         ctypes.POINTER(Info), _vp]
+        L.pmgw_adjoint_apply.argtypes = [_vp, _vp, _vp]
+        L.pmgw_adjoint_vcycle.argtypes = [_vp, _vp, _vp]
         L.pmgw_plan_destroy.argtypes = [_vp]
         L.pmgw_plan_destroy.restype = None
         L.pmgw_last_error.restype = ctypes.c_char_p
@@ -230,12 +232,33 @@ def pmg_vcycle(plan, r, z):
 
 def poisson_solve(plan, b, p, rtol=1e-10, maxit=100, sync=True, info_dev=None):
     """Returns a list of (iters, status, relres) per tank when sync, else None."""
+    return _solve("poisson_solve", plan, b, p, rtol, maxit, sync, info_dev)
+
+
+def adjoint_solve(plan, g, lam, rtol=1e-10, maxit=100, sync=True, info_dev=None):
+    """lam = A^-T g (lam holds the initial guess). Returns per-tank info like poisson_solve."""
+    return _solve("pmgw_adjoint_solve", plan, g, lam, rtol, maxit, sync, info_dev)
+
+
+def adjoint_apply(plan, lam, out):
+    import torch
+    _check(lib().pmgw_adjoint_apply(plan._h, _ptr(lam, torch.float64), _ptr(out, torch.float64)))
+    _trace("pmgw_adjoint_apply")
+
+
+def adjoint_vcycle(plan, r, z):
+    import torch
+    _check(lib().pmgw_adjoint_vcycle(plan._h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
+    _trace("pmgw_adjoint_vcycle")
+
+
+def _solve(name, plan, b, p, rtol, maxit, sync, info_dev):
     import torch
     infos = (Info * plan.ntanks)() if sync else None
     dptr = _ptr(info_dev) if info_dev is not None else None
-    rc = lib().poisson_solve(plan._h, _ptr(b, torch.float64), _ptr(p, torch.float64),
-                             float(rtol), int(maxit), infos, dptr)
-    _trace("poisson_solve")
+    rc = getattr(lib(), name)(plan._h, _ptr(b, torch.float64), _ptr(p, torch.float64),
+                              float(rtol), int(maxit), infos, dptr)
+    _trace(name)
     if rc < 0:
         msg = lib().pmgw_last_error().decode()
         out = [(i.iters, i.status, i.relres) for i in infos] if infos is not None else None
@@ -246,7 +269,7 @@ def poisson_solve(plan, b, p, rtol=1e-10, maxit=100, sync=True, info_dev=None):
         return None
     out = [(i.iters, i.status, i.relres) for i in infos]
     if rc == NOCONV:
-        warnings.warn("poisson_solve: a tank did not converge: " +
+        warnings.warn(name + ": a tank did not converge: " +
                       lib().pmgw_last_error().decode())
     return out
 
