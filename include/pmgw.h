@@ -178,6 +178,22 @@ int pmgw_adjoint_vcycle(pmgw_plan plan, const double* r, double* z);
 int pmgw_adjoint_solve(pmgw_plan plan, const double* g, double* lambda, double rtol,
                        int32_t maxit, pmgw_info* info_host, pmgw_info* info_dev);
 
+/*
+ * Reverse of rk4_stage (its discrete adjoint), for gradients through time stepping.
+ * u, w, eta, Ku, Kw, Keta: the stage's INPUT state (as passed to rk4_stage; unchanged here).
+ * ub, wb, etab, Kub, Kwb, Ketab: on entry the adjoints of the stage's outputs, on exit the
+ * adjoints of its inputs (in place). hbar: adjoint of the depth h, ACCUMULATED (+=).
+ * The call recomputes the stage's intermediates (including its pressure solve, to rtol) in the
+ * workspace, then solves one adjoint system A^T lambda = pbar (pmgw_adjoint_solve, to rtol;
+ * its info goes to info_dev when non-NULL). The forward solve is differentiated as exact.
+ * The plan's geometry is left at the stage's (eta^(k-1), eta^(k)).
+ */
+int rk4_stage_adjoint(pmgw_plan plan, int32_t k, double dt, const double* h, const double* u,
+                      const double* w, const double* eta, const double* Ku, const double* Kw,
+                      const double* Keta, double* ub, double* wb, double* etab, double* Kub,
+                      double* Kwb, double* Ketab, double* hbar, double rtol, int32_t maxit,
+                      pmgw_info* info_dev);
+
 /* Release the plan (not the workspace, which the caller owns). NULL is ignored. */
 void pmgw_plan_destroy(pmgw_plan plan);
 

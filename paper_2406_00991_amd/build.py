@@ -26,14 +26,19 @@ def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def check_device_asm(verbose=False):
-    """Compile the device code to assembly; return per-kernel resource usage. Raises on long
-    branches."""
-    with tempfile.TemporaryDirectory() as td:
-        asm = os.path.join(td, "dev.s")
-        subprocess.run([_hipcc(), *FLAGS, "--cuda-device-only", "-S", SRC, "-o", asm], check=True,
-                       stderr=subprocess.DEVNULL)
-        text = open(asm).read()
+def _asm_cmd(asm):
+    return [_hipcc(), *FLAGS, "--cuda-device-only", "-S", SRC, "-o", asm]
+
+
+def check_device_asm(verbose=False, asm_text=None):
+    """Compile the device code to assembly (unless given); return per-kernel resource usage.
+    Raises on long branches."""
+    if asm_text is None:
+        with tempfile.TemporaryDirectory() as td:
+            asm = os.path.join(td, "dev.s")
+            subprocess.run(_asm_cmd(asm), check=True, stderr=subprocess.DEVNULL)
+            asm_text = open(asm).read()
+    text = asm_text
     if ".Lpost_getpc" in text:
         raise RuntimeError("device code contains long-branch sequences (s_getpc/s_setpc); "
                            "split or shrink the offending function")
@@ -52,13 +57,23 @@ def check_device_asm(verbose=False):
 
 
 def build(verbose=False, check=True):
+    """Compile the library and (concurrently) the device assembly for the check."""
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), *FLAGS, "-fPIC", "-shared", SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    if check:
-        check_device_asm(verbose)
+    with tempfile.TemporaryDirectory() as td:
+        asm = os.path.join(td, "dev.s")
+        chk = subprocess.Popen(_asm_cmd(asm), stderr=subprocess.DEVNULL) if check else None
+        lib = subprocess.Popen(cmd)
+        rc_lib = lib.wait()
+        rc_chk = chk.wait() if chk else 0
+        if rc_lib != 0:
+            raise subprocess.CalledProcessError(rc_lib, cmd)
+        if rc_chk != 0:
+            raise subprocess.CalledProcessError(rc_chk, _asm_cmd(asm))
+        if check:
+            check_device_asm(verbose, open(asm).read())
     os.replace(tmp, LIB)
     return LIB
 

@@ -11,6 +11,7 @@
 #include "../../include/pmgw.h"
 #include "pmgw_kernels.hpp"
 #include "pmgw_rk.hpp"
+#include "pmgw_rka.hpp"
 
 using namespace pmgw;
 
@@ -174,7 +175,7 @@ struct pmgw_plan_s {
   std::vector<int64_t> off2d, off1d;
   // constant image: [descs][jobs][per-tank tables...] copied at bind time
   std::vector<char> image;
-  int64_t desc_off = 0, job_off = 0, info_off = 0, rk_off = 0;
+  int64_t desc_off = 0, job_off = 0, info_off = 0, rk_off = 0, adj_off = 0;
   // tanks grouped by finest-level row count (3, 5, 9, 17, 33): one solve launch per class
   int64_t ids_off[5] = {0, 0, 0, 0, 0};
   std::vector<int32_t> ids[5];
@@ -436,6 +437,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   }
   p->rk_off = cur;
   cur = align256(cur + rk_workspace_bytes(p->off2d[ntanks], p->off1d[ntanks]));
+  p->adj_off = cur;
+  cur = align256(cur + adj_workspace_bytes(p->off2d[ntanks], p->off1d[ntanks]));
   p->total = cur;
 
   // block-inversion jobs
@@ -757,3 +760,109 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   return launch_rk_all(p, 2, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
 }
 
+namespace {
+
+template <int NZ>
+void launch_rka(pmgw_plan p, int c, int which, const RkCoef& cf, const double* u,
+                const double* w, double* ub, double* wb, double* etab, double* Kub, double* Kwb,
+                double* Ketab, double* hbar, const RkBufs& rb, const AdjBufs& ab) {
+  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
+  const unsigned nt = (unsigned)p->ids[c].size();
+  const int fftb = 32768;
+  const size_t lds = (size_t)(2 * fftb);
+  if (which == 0)
+    hipLaunchKernelGGL(k_rka_post<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
+                       ub, wb, Kub, Kwb, rb, ab, fftb);
+  else if (which == 1)
+    hipLaunchKernelGGL(k_rka_mid<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
+                       ub, wb, Kub, Kwb, rb, ab, fftb);
+  else if (which == 2)
+    hipLaunchKernelGGL(k_rka_force<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
+                       u, w, ub, wb, rb, ab, fftb);
+  else
+    hipLaunchKernelGGL(k_rka_pre<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
+                       u, ub, wb, etab, Ketab, hbar, rb, ab, fftb);
+}
+
+int launch_rka_all(pmgw_plan p, int which, const RkCoef& cf, const double* u, const double* w,
+                   double* ub, double* wb, double* etab, double* Kub, double* Kwb, double* Ketab,
+                   double* hbar, const RkBufs& rb, const AdjBufs& ab) {
+  if (!p->ids[0].empty()) launch_rka<3>(p, 0, which, cf, u, w, ub, wb, etab, Kub, Kwb, Ketab, hbar, rb, ab);
+  if (!p->ids[1].empty()) launch_rka<5>(p, 1, which, cf, u, w, ub, wb, etab, Kub, Kwb, Ketab, hbar, rb, ab);
+  if (!p->ids[2].empty()) launch_rka<9>(p, 2, which, cf, u, w, ub, wb, etab, Kub, Kwb, Ketab, hbar, rb, ab);
+  if (!p->ids[3].empty()) launch_rka<17>(p, 3, which, cf, u, w, ub, wb, etab, Kub, Kwb, Ketab, hbar, rb, ab);
+  if (!p->ids[4].empty()) launch_rka<33>(p, 4, which, cf, u, w, ub, wb, etab, Kub, Kwb, Ketab, hbar, rb, ab);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "adjoint stage kernel launch");
+  return PMGW_OK;
+}
+
+int fill_zero_dev(pmgw_plan p, double* a, int64_t n) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, p->stream, a, n, 0.0);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "fill kernel launch");
+  return PMGW_OK;
+}
+
+}  // namespace
+
+extern "C" int rk4_stage_adjoint(pmgw_plan p, int32_t k, double dt, const double* h,
+                                 const double* u, const double* w, const double* eta,
+                                 const double* Ku, const double* Kw, const double* Keta,
+                                 double* ub, double* wb, double* etab, double* Kub, double* Kwb,
+                                 double* Ketab, double* hbar, double rtol, int32_t maxit,
+                                 pmgw_info* info_dev) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (k < 1 || k > 5) return fail(PMGW_EINVAL, "stage k must be in 1..5");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PMGW_EINVAL, "dt must be positive");
+  if (!h || !u || !w || !eta || !Ku || !Kw || !Keta || !ub || !wb || !etab || !Kub || !Kwb ||
+      !Ketab || !hbar)
+    return fail(PMGW_EINVAL, "fields must be non-NULL");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PMGW_EINVAL, "rtol must be positive");
+  if (maxit < 1) return fail(PMGW_EINVAL, "maxit must be >= 1");
+  RkCoef cf;
+  cf.a = kCkAlpha[k - 1];
+  cf.b = kCkBeta[k - 1];
+  cf.dt = dt;
+  cf.rho = p->opts.rho;
+  cf.g = p->opts.g;
+  cf.nu = p->opts.nu_visc;
+  const int64_t n2d = p->off2d[p->ntanks], n1d = p->off1d[p->ntanks];
+  const RkBufs rb = rk_bufs(p->ws + p->rk_off, n2d, n1d);
+  const AdjBufs ab = adj_bufs(p->ws + p->adj_off, n2d, n1d);
+  // forward recompute of the stage's intermediates (the caller's state is left untouched)
+  hipError_t e = hipMemcpyAsync(ab.eta1, eta, 8 * n1d, hipMemcpyDeviceToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ab.keta1, Keta, 8 * n1d, hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "state copy");
+  double* cu = const_cast<double*>(u);
+  double* cw = const_cast<double*>(w);
+  double* cku = const_cast<double*>(Ku);
+  double* ckw = const_cast<double*>(Kw);
+  rc = launch_rk_all(p, 0, cf, cu, cw, ab.eta1, cku, ckw, ab.keta1, nullptr, rb);
+  if (rc) return rc;
+  rc = pmgw_set_geometry(p, h, rb.eo, ab.eta1);
+  if (rc) return rc;
+  rc = launch_rk_all(p, 1, cf, cu, cw, ab.eta1, cku, ckw, ab.keta1, nullptr, rb);
+  if (rc) return rc;
+  pmgw_info_dev* iinfo = reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
+  pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev) : iinfo;
+  if ((rc = fill_zero_dev(p, ab.p, n2d))) return rc;
+  rc = launch_solve(p, MODE_SOLVE, rb.b, ab.p, rtol, maxit, iinfo);
+  if (rc) return rc;
+  // reverse steps
+  rc = launch_rka_all(p, 0, cf, u, w, ub, wb, etab, Kub, Kwb, Ketab, hbar, rb, ab);
+  if (rc) return rc;
+  if ((rc = fill_zero_dev(p, ab.lam, n2d))) return rc;
+  rc = launch_solve(p, MODE_SOLVE, ab.pb, ab.lam, rtol, maxit, dinfo, true);
+  if (rc) return rc;
+  for (int which = 1; which <= 3; ++which) {
+    rc = launch_rka_all(p, which, cf, u, w, ub, wb, etab, Kub, Kwb, Ketab, hbar, rb, ab);
+    if (rc) return rc;
+  }
+  return PMGW_OK;
+}

@@ -85,6 +85,13 @@ __device__ __forceinline__ LevSet<T> uni(const LevSet<T>& s) {
   return LevSet<T>{uni(s.ws), uni(s.td), uni(s.f0), uni(s.x0)};
 }
 
+// a[e] = v for e < n (grid-stride).
+__global__ void __launch_bounds__(256) k_fill(double* a, int64_t n, double v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    a[e] = v;
+}
+
 // ----------------------------------------------------------------------------- geometry kernel
 
 constexpr int kGeoFftBytes = 32768;   // the geometry kernel runs with 2 x 32 KB of FFT LDS

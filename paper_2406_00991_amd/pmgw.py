@@ -73,6 +73,8 @@ def lib():
         L.pmgw_adjoint_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.POINTER(Info), _vp]
         L.pmgw_adjoint_apply.argtypes = [_vp, _vp, _vp]
+        L.rk4_stage_adjoint.argtypes = ([_vp, ctypes.c_int32, ctypes.c_double] + [_vp] * 14 +
+                                        [ctypes.c_double, ctypes.c_int32, _vp])
         L.pmgw_adjoint_vcycle.argtypes = [_vp, _vp, _vp]
         L.pmgw_plan_destroy.argtypes = [_vp]
         L.pmgw_plan_destroy.restype = None
@@ -283,6 +285,21 @@ def rk4_stage(plan, k, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10, maxit=100,
                            _ptr(eta, f64), _ptr(Ku, f64), _ptr(Kw, f64), _ptr(Keta, f64),
                            _ptr(p, f64), float(rtol), int(maxit), dptr))
     _trace("rk4_stage")
+
+
+def rk4_stage_adjoint(plan, k, dt, h, state, bar, hbar, rtol=1e-12, maxit=200, info_dev=None):
+    """Reverse of stage k. state: dict u, w, eta, Ku, Kw, Keta of the stage's INPUT state (left
+    unchanged). bar: dict of the same keys holding the adjoints of the stage's outputs, replaced
+    in place by the adjoints of its inputs. hbar is accumulated."""
+    import torch
+    f64 = torch.float64
+    keys = ("u", "w", "eta", "Ku", "Kw", "Keta")
+    dptr = _ptr(info_dev) if info_dev is not None else None
+    _check(lib().rk4_stage_adjoint(plan._h, int(k), float(dt), _ptr(h, f64),
+                                   *[_ptr(state[q], f64) for q in keys],
+                                   *[_ptr(bar[q], f64) for q in keys], _ptr(hbar, f64),
+                                   float(rtol), int(maxit), dptr))
+    _trace("rk4_stage_adjoint")
 
 
 def rk4_step(plan, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10, maxit=100, info_dev=None):

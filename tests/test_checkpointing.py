@@ -1,0 +1,70 @@
+"""Host logic of the checkpointed reverse sweep (paper_2406_00991_amd.autograd), on the CPU.
+
+The library calls are replaced by the oracle's forward stage and reverse stage on CPU tensors, so
+that only the ordering of the sweep is under test: checkpoints every C steps (C dividing the step
+count or not), recomputation of each segment's stage inputs, and the reverse order of the stage
+adjoints. The result must equal the oracle's gradient taken without checkpoints.
+"""
+import types
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as adj
+from oracle import lserk
+from oracle import spectral as sp
+from paper_2406_00991_amd import autograd as ag
+from paper_2406_00991_amd import workloads as wl
+
+
+class FakeLib:
+    def __init__(self, nx, nz, L):
+        self.nx, self.nz, self.L = nx, nz, L
+        self.calls = []
+
+    def _state(self, u, w, eta, Ku, Kw, Keta, p):
+        r2 = lambda t: t.numpy().reshape(self.nz, self.nx).copy()
+        return lserk.State(r2(u), r2(w), eta.numpy().copy(), r2(Ku), r2(Kw), Keta.numpy().copy(),
+                           r2(p))
+
+    def rk4_stage(self, plan, k, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=0, maxit=0):
+        s = self._state(u, w, eta, Ku, Kw, Keta, p)
+        lserk.stage(k, dt, h.numpy(), self.L, s, lserk.dense_solver)
+        for t, a in ((u, s.u), (w, s.w), (eta, s.eta), (Ku, s.Ku), (Kw, s.Kw), (Keta, s.Keta),
+                     (p, s.p)):
+            t.copy_(torch.from_numpy(np.ascontiguousarray(a).ravel()))
+        self.calls.append(("f", k))
+
+    def rk4_stage_adjoint(self, plan, k, dt, h, st, bar, hbar, rtol=0, maxit=0, info_dev=None):
+        s = self._state(*(st[q] for q in ("u", "w", "eta", "Ku", "Kw", "Keta", "p")))
+        tp = adj.stage_tape(k, dt, h.numpy(), self.L, s)
+        b = {q: (bar[q].numpy().reshape(self.nz, self.nx) if q not in ("eta", "Keta")
+                 else bar[q].numpy()) for q in bar}
+        out, hb = adj.stage_T(tp, b, h.numpy(), self.L)
+        for q in bar:
+            bar[q].copy_(torch.from_numpy(np.ascontiguousarray(out[q]).ravel()))
+        hbar += torch.from_numpy(hb)
+        self.calls.append(("r", k))
+
+
+@pytest.mark.parametrize("checkpoint", [1, 2, 3])
+def test_checkpointed_sweep_equals_plain_gradient(monkeypatch, checkpoint):
+    nx, nz, nsteps, probe = 16, 5, 3, 7
+    wv = dict(wl.stokes_wave(nx, nz, steep=0.02))
+    wv["h"] = wv["h"] + 0.03 * np.sin(sp.x_nodes(nx, wv["L"]))
+    fake = FakeLib(nx, nz, wv["L"])
+    monkeypatch.setattr(ag, "pmgw", types.SimpleNamespace(rk4_stage=fake.rk4_stage,
+                                                          rk4_stage_adjoint=fake.rk4_stage_adjoint))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel().copy())
+    st0 = ag.initial_state(t(wv["u"]), t(wv["w"]), t(wv["eta"]))
+    geta = torch.zeros(nx, dtype=torch.float64)
+    geta[probe] = 1.0
+    hbar, _ = ag.gradient(None, t(wv["h"]), st0, wv["dt"], nsteps, dict(eta=geta), checkpoint)
+    ref = adj.probe_gradient(wv["h"], wv["L"], dict(u=wv["u"], w=wv["w"], eta=wv["eta"]),
+                             wv["dt"], nsteps, probe)
+    assert np.abs(hbar.numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    rev = [k for kind, k in fake.calls if kind == "r"]
+    assert rev == [5, 4, 3, 2, 1] * nsteps
+    fwd = sum(1 for kind, _ in fake.calls if kind == "f")
+    assert fwd == 2 * 5 * nsteps          # the checkpointed run plus one recompute per segment

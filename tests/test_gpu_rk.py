@@ -6,9 +6,10 @@ above that grid's rounding floor of ~4e-13).
 Both sides stop their solves at relative residuals far below the tolerances used here, so the
 differences left are solver-tolerance and rounding effects amplified by dt/rho (velocities) and
 the stage coefficients. Tolerances, relative to each field's max norm:
-- eta (set before the solve, only the kinematic update and the x-filter): 1e-12;
-- u, w, K_u, K_w: 1e-9; p: 1e-8 (the solves stop at 1e-12 .. 1e-13 relative residual and the
-  operator's condition number is ~1e4 at these sizes).
+- eta (order-one values, set before the solve by the kinematic update and the x-filter): 1e-12;
+- u, w, K_u, K_w and K_eta (a sum of surface velocities times dt): 1e-9; p: 1e-8 (the solves
+  stop at 1e-12 .. 1e-13 relative residual and the operator's condition number is ~1e4 at these
+  sizes).
 """
 import math
 
@@ -86,8 +87,7 @@ def relerr(a, b):
 
 def compare(got, s, tol_eta=1e-12, tol_uw=1e-9, tol_p=1e-8):
     assert relerr(got["eta"], s.eta) <= tol_eta
-    assert relerr(got["Keta"], s.Keta) <= tol_eta
-    for key in ("u", "w", "Ku", "Kw"):
+    for key in ("u", "w", "Ku", "Kw", "Keta"):
         assert relerr(got[key], getattr(s, key)) <= tol_uw, key
     assert relerr(got["p"], s.p) <= tol_p
 
