@@ -38,7 +38,7 @@ class PmgOptions:
     nu2: int = 1
     omega_c: float = 1.0
     omega_m: float = 1.0
-    coarse_pairs: int = 4
+    coarse_pairs: int = 2
     coarse: str = "smooth"        # "smooth" (fixed pairs) or "exact" (dense LU)
 
 

@@ -2,6 +2,7 @@
 // tables, argument validation and kernel launches behind the C ABI declared in pmgw.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -179,6 +180,8 @@ struct pmgw_plan_s {
   // tanks grouped by finest-level row count (3, 5, 9, 17, 33): one solve launch per class
   int64_t ids_off[5] = {0, 0, 0, 0, 0};
   std::vector<int32_t> ids[5];
+  int maxnx[5] = {0, 0, 0, 0, 0};   // largest Nx per class (sizes the LDS twiddle tables)
+  int maxnx_all = 0;
   int64_t total = 0;
   char* ws = nullptr;
   bool geometry_set = false;
@@ -187,9 +190,19 @@ struct pmgw_plan_s {
   std::vector<hipEvent_t> ev0, ev1;
   int prof_n = 0;
   bool prof_on = false;
+  // side streams (default priority) and events that run the Nz classes of one solve call
+  // concurrently, forked from and joined back to `stream`; created on first use
+  hipStream_t side[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int nclasses = 0;
   ~pmgw_plan_s() {
     for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev1) (void)hipEventDestroy(e);
+    for (int c = 0; c < 5; ++c) {
+      if (side[c]) (void)hipStreamDestroy(side[c]);
+      if (join[c]) (void)hipEventDestroy(join[c]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
   }
 };
 
@@ -220,6 +233,10 @@ KOpts kopts(const pmgw_plan_s* p) {
   return o;
 }
 
+// Dynamic LDS of a launch that runs FFTs: two FFT halves of fftb bytes, then the float64 and
+// float32 twiddle tables of the largest Nx.
+size_t lds_bytes(int fftb, int maxnx) { return (size_t)(2 * fftb) + (size_t)24 * maxnx; }
+
 int nz_class(int nz) { return nz == 3 ? 0 : nz == 5 ? 1 : nz == 9 ? 2 : nz == 17 ? 3 : 4; }
 
 // Largest workgroup the solve kernel is compiled for (its register budget follows from it).
@@ -227,7 +244,7 @@ constexpr int kSolveMaxThreads = 256;
 
 template <typename TV, int NZ, bool TR>
 void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, double rtol,
-                  int maxit, pmgw_info_dev* info, const KOpts& o) {
+                  int maxit, pmgw_info_dev* info, const KOpts& o, hipStream_t st) {
   const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
   const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
   const int nt = (int)p->ids[c].size();
@@ -235,18 +252,60 @@ void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, d
   const int thr = p->opts.threads ? p->opts.threads : MAXT;
   // Two halves of 32 KB of FFT LDS per workgroup: two workgroups fit on one CU.
   const int fftb = 32768;
-  hipLaunchKernelGGL((k_solve<TV, NZ, MAXT, TR>), dim3((unsigned)nt), dim3(thr), (size_t)(2 * fftb),
-                     p->stream, d, ids, p->ws, mode, in, out, rtol, maxit, info, o, fftb);
+  hipLaunchKernelGGL((k_solve<TV, NZ, MAXT, TR>), dim3((unsigned)nt), dim3(thr),
+                     lds_bytes(fftb, p->maxnx[c]), st, d, ids, p->ws, mode, in, out, rtol, maxit,
+                     info, o, fftb);
 }
 
+// Creates the side streams and fork/join events once (only plans with several Nz classes).
+int ensure_side_streams(pmgw_plan p) {
+  if (p->fork) return PMGW_OK;
+  hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+  for (int c = 0; c < 5 && e == hipSuccess; ++c) {
+    if (p->ids[c].empty()) continue;
+    e = hipStreamCreateWithFlags(&p->side[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[c], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) return hip_fail(e, "creating side streams");
+  return PMGW_OK;
+}
+
+// One solve-kernel launch per Nz class. With several classes the launches go to side streams
+// that wait on an event recorded on the plan's stream and are joined back into it, so that the
+// classes run concurrently (a 512-tank batch has three classes); the order seen by later work on
+// the plan's stream is unchanged, and the fork/join pattern is valid under graph capture.
 template <typename TV, bool TR>
-void launch_all(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
-                pmgw_info_dev* info, const KOpts& o) {
-  if (!p->ids[0].empty()) launch_class<TV, 3, TR>(p, 0, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[1].empty()) launch_class<TV, 5, TR>(p, 1, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[2].empty()) launch_class<TV, 9, TR>(p, 2, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[3].empty()) launch_class<TV, 17, TR>(p, 3, mode, in, out, rtol, maxit, info, o);
-  if (!p->ids[4].empty()) launch_class<TV, 33, TR>(p, 4, mode, in, out, rtol, maxit, info, o);
+int launch_all(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
+               pmgw_info_dev* info, const KOpts& o) {
+  const bool multi = p->nclasses > 1;
+  if (multi) {
+    int rc = ensure_side_streams(p);
+    if (rc) return rc;
+    hipError_t e = hipEventRecord(p->fork, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "fork event");
+  }
+  for (int c = 0; c < 5; ++c) {
+    if (p->ids[c].empty()) continue;
+    hipStream_t st = p->stream;
+    if (multi) {
+      st = p->side[c];
+      hipError_t e = hipStreamWaitEvent(st, p->fork, 0);
+      if (e != hipSuccess) return hip_fail(e, "side stream wait");
+    }
+    switch (c) {
+      case 0: launch_class<TV, 3, TR>(p, 0, mode, in, out, rtol, maxit, info, o, st); break;
+      case 1: launch_class<TV, 5, TR>(p, 1, mode, in, out, rtol, maxit, info, o, st); break;
+      case 2: launch_class<TV, 9, TR>(p, 2, mode, in, out, rtol, maxit, info, o, st); break;
+      case 3: launch_class<TV, 17, TR>(p, 3, mode, in, out, rtol, maxit, info, o, st); break;
+      default: launch_class<TV, 33, TR>(p, 4, mode, in, out, rtol, maxit, info, o, st); break;
+    }
+    if (multi) {
+      hipError_t e = hipEventRecord(p->join[c], st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->join[c], 0);
+      if (e != hipSuccess) return hip_fail(e, "join event");
+    }
+  }
+  return PMGW_OK;
 }
 
 // tr: the transposed operator and cycle (adjoint solves).
@@ -255,13 +314,14 @@ int launch_solve(pmgw_plan p, int mode, const double* in, double* out, double rt
   const KOpts o = kopts(p);
   const bool timed = p->prof_on && mode == MODE_SOLVE && !tr && p->prof_n < (int)p->ev0.size();
   if (timed) (void)hipEventRecord(p->ev0[p->prof_n], p->stream);
-  if (p->prec == PMGW_FP64) {
-    if (tr) launch_all<double, true>(p, mode, in, out, rtol, maxit, info, o);
-    else launch_all<double, false>(p, mode, in, out, rtol, maxit, info, o);
-  } else {
-    if (tr) launch_all<float, true>(p, mode, in, out, rtol, maxit, info, o);
-    else launch_all<float, false>(p, mode, in, out, rtol, maxit, info, o);
-  }
+  int rc;
+  if (p->prec == PMGW_FP64)
+    rc = tr ? launch_all<double, true>(p, mode, in, out, rtol, maxit, info, o)
+            : launch_all<double, false>(p, mode, in, out, rtol, maxit, info, o);
+  else
+    rc = tr ? launch_all<float, true>(p, mode, in, out, rtol, maxit, info, o)
+            : launch_all<float, false>(p, mode, in, out, rtol, maxit, info, o);
+  if (rc) return rc;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "solve kernel launch");
   if (timed) (void)hipEventRecord(p->ev1[p->prof_n++], p->stream);
@@ -283,7 +343,7 @@ void pmgw_default_opts(pmgw_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->nu1 = 1;
   o->nu2 = 1;
-  o->coarse_pairs = 4;
+  o->coarse_pairs = 2;
   o->restart = 30;
   o->omega_c = 1.0;
   o->omega_m = 1.0;
@@ -359,8 +419,18 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   cur = align256(cur + (int64_t)sizeof(BlockJob) * njobs);
   p->info_off = cur;
   cur = align256(cur + (int64_t)sizeof(pmgw_info) * ntanks);
-  for (int t = 0; t < ntanks; ++t) p->ids[nz_class(nz[t])].push_back(t);
+  for (int t = 0; t < ntanks; ++t) {
+    const int c = nz_class(nz[t]);
+    p->ids[c].push_back(t);
+    p->maxnx[c] = std::max(p->maxnx[c], (int)nx[t]);
+    p->maxnx_all = std::max(p->maxnx_all, (int)nx[t]);
+  }
   for (int c = 0; c < 5; ++c) {
+    // largest tanks first: the hardware dispatches workgroups in order, so the longest solves
+    // start earliest
+    std::stable_sort(p->ids[c].begin(), p->ids[c].end(),
+                     [&](int32_t a, int32_t b) { return nx[a] > nx[b]; });
+    if (!p->ids[c].empty()) ++p->nclasses;
     p->ids_off[c] = cur;
     cur = align256(cur + 4 * (int64_t)p->ids[c].size());
   }
@@ -541,7 +611,7 @@ int pmgw_set_geometry(pmgw_plan p, const double* h, const double* eo, const doub
   if (!h || !eo || !en) return fail(PMGW_EINVAL, "h, eta_old and eta_new must be non-NULL");
   const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
   const BlockJob* j = reinterpret_cast<const BlockJob*>(p->ws + p->job_off);
-  hipLaunchKernelGGL(k_geometry, dim3(p->ntanks), dim3(256), (size_t)(2 * kGeoFftBytes), p->stream,
+  hipLaunchKernelGGL(k_geometry, dim3(p->ntanks), dim3(256), lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream,
                      d, p->ws, h, eo, en);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
@@ -703,13 +773,13 @@ void launch_rk(pmgw_plan p, int c, int which, const RkCoef& cf, const double* u,
   const unsigned nt = (unsigned)p->ids[c].size();
   const int fftb = 32768;
   if (which == 0)
-    hipLaunchKernelGGL(k_rk_pre<NZ>, dim3(nt), dim3(256), (size_t)(2 * fftb), p->stream, d, ids,
+    hipLaunchKernelGGL(k_rk_pre<NZ>, dim3(nt), dim3(256), lds_bytes(fftb, p->maxnx[c]), p->stream, d, ids,
                        p->ws, cf, u, w, eta, Keta, rb, fftb);
   else if (which == 1)
-    hipLaunchKernelGGL(k_rk_force<NZ>, dim3(nt), dim3(256), (size_t)(2 * fftb), p->stream, d, ids,
+    hipLaunchKernelGGL(k_rk_force<NZ>, dim3(nt), dim3(256), lds_bytes(fftb, p->maxnx[c]), p->stream, d, ids,
                        p->ws, cf, u, w, (const double*)Ku, (const double*)Kw, rb, fftb);
   else
-    hipLaunchKernelGGL(k_rk_post<NZ>, dim3(nt), dim3(256), (size_t)(2 * fftb), p->stream, d, ids,
+    hipLaunchKernelGGL(k_rk_post<NZ>, dim3(nt), dim3(256), lds_bytes(fftb, p->maxnx[c]), p->stream, d, ids,
                        p->ws, cf, pr, uo, wo, Ku, Kw, rb, fftb);
 }
 
@@ -770,7 +840,7 @@ void launch_rka(pmgw_plan p, int c, int which, const RkCoef& cf, const double* u
   const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
   const unsigned nt = (unsigned)p->ids[c].size();
   const int fftb = 32768;
-  const size_t lds = (size_t)(2 * fftb);
+  const size_t lds = lds_bytes(fftb, p->maxnx[c]);
   if (which == 0)
     hipLaunchKernelGGL(k_rka_post<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
                        ub, wb, Kub, Kwb, rb, ab, fftb);

@@ -95,10 +95,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // (row r at a + r N), ping-ponging with b. One radix-2 pass first when log2N is odd, then
 // radix-4 passes; p is the length of the sub-transforms already done. Returns the buffer that
 // holds the (natural-order) result. Forward: exp(-2 pi i / N) kernel; inverse: conjugate,
-// unscaled. tw[t] = exp(-2 pi i t / N) for t < N.
+// unscaled. tw[t] = exp(-2 pi i t / N) for t < N, in LDS (see lds_tw).
 template <typename T, bool INV>
 __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int nrows, int N, int log2N,
-                           gptr<const cpx<T>> __restrict__ tw) {
+                           const cpx<T>* __restrict__ tw) {
   int p = 1;
   if (log2N & 1) {
     const int h = N >> 1, items = nrows << (log2N - 1);
@@ -124,7 +124,7 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, int nrows, int N, int log2N,
       cpx<T> u0 = s[i], u1 = s[i + q], u2 = s[i + 2 * q], u3 = s[i + 3 * q];
       if (p > 1) {
         const int t = k * tstep;
-        cpx<T> w1 = gld<T>(tw, t), w2 = gld<T>(tw, 2 * t), w3 = gld<T>(tw, 3 * t);
+        cpx<T> w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t];
         if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
         u1 = cmul(u1, w1);
         u2 = cmul(u2, w2);
@@ -159,6 +159,26 @@ __device__ __forceinline__ cpx<T>* fft_buf() {
 template <typename T>
 __device__ __forceinline__ int fft_cap(int fftb) { return fftb / (int)sizeof(cpx<T>); }
 
+// Twiddle tables in LDS, after the two FFT halves: N float64 values, then N float32 values.
+// A launch whose kernels run FFTs reserves 2 fftb + 24 N bytes of dynamic LDS (N = the largest
+// Nx among its tanks), and the kernel copies its tank's tables there first (stage_twiddles).
+template <typename T>
+__device__ __forceinline__ cpx<T>* lds_tw(int fftb, int N) {
+  char* b = reinterpret_cast<char*>(g_fft_lds) + 2 * fftb + (sizeof(T) == 4 ? 16 * N : 0);
+  return reinterpret_cast<cpx<T>*>(b);
+}
+
+__device__ __forceinline__ void stage_twiddles(gptr<const cpx<double>> t64,
+                                               gptr<const cpx<float>> t32, int N, int fftb) {
+  cpx<double>* d = lds_tw<double>(fftb, N);
+  cpx<float>* f = lds_tw<float>(fftb, N);
+  for (int t = tid(); t < N; t += nthr()) {
+    d[t] = gld<double>(t64, t);
+    f[t] = gld<float>(t32, t);
+  }
+  __syncthreads();
+}
+
 // Orders LDS accesses of one wavefront: every lane's earlier LDS writes are seen by the later
 // reads of the other lanes of the same wavefront (LDS executes a wavefront's operations in
 // order; this keeps the compiler from moving them across).
@@ -172,7 +192,7 @@ __device__ __forceinline__ void wave_sync() {
 // in place: each pass reads its inputs into registers (at most 8 complex values per lane),
 // synchronises the wavefront, and writes its outputs over them.
 template <typename T, bool INV>
-__device__ void fft_wave(cpx<T>* a, int N, int log2N, gptr<const cpx<T>> __restrict__ tw, int lane) {
+__device__ void fft_wave(cpx<T>* a, int N, int log2N, const cpx<T>* __restrict__ tw, int lane) {
   cpx<T> r[8];
   int p = 1;
   if (log2N & 1) {
@@ -214,7 +234,7 @@ __device__ void fft_wave(cpx<T>* a, int N, int log2N, gptr<const cpx<T>> __restr
         cpx<T> u0 = r[4 * it], u1 = r[4 * it + 1], u2 = r[4 * it + 2], u3 = r[4 * it + 3];
         if (p > 1) {
           const int t = k * tstep;
-          cpx<T> w1 = gld<T>(tw, t), w2 = gld<T>(tw, 2 * t), w3 = gld<T>(tw, 3 * t);
+          cpx<T> w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t];
           if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
           u1 = cmul(u1, w1);
           u2 = cmul(u2, w2);
@@ -285,9 +305,9 @@ __device__ __forceinline__ bool fft_by_wave(int N, int fftb) {
 // row j at column i; sm(k, v) returns m_k v / N for the unscaled inverse FFT; st(j, i, v) writes
 // the result. fftb: bytes of one half of the FFT LDS buffer. Ends with a barrier.
 template <typename T, class LD, class SM, class ST>
-__device__ void spectral_rows(int nrows, int N, int log2N, gptr<const cpx<T>> __restrict__ tw,
-                              int fftb, LD ld, SM sm, ST st) {
+__device__ void spectral_rows(int nrows, int N, int log2N, int fftb, LD ld, SM sm, ST st) {
   const int npairs = (nrows + 1) >> 1;
+  const cpx<T>* tw = lds_tw<T>(fftb, N);
   if (fft_by_wave<T>(N, fftb)) {
     const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
     cpx<T>* A = fft_buf<T>() + w * N;
@@ -334,11 +354,10 @@ __device__ void spectral_rows(int nrows, int N, int log2N, gptr<const cpx<T>> __
 
 // D_x of `nrows` real rows: the spectral multiplier i kappa_k / N with the Nyquist entry zeroed.
 template <typename T, class LD, class ST>
-__device__ __forceinline__ void dx_rows(int nrows, int N, int log2N, T kfac,
-                                        gptr<const cpx<T>> __restrict__ tw, int fftb, LD ld,
+__device__ __forceinline__ void dx_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld,
                                         ST st) {
   const T scale = T(1) / T(N);
-  spectral_rows<T>(nrows, N, log2N, tw, fftb, ld,
+  spectral_rows<T>(nrows, N, log2N, fftb, ld,
                    [=](int n, cpx<T> v) {
                      const int kk = (n <= (N >> 1)) ? n : n - N;
                      const T kap = (n == (N >> 1)) ? T(0) : kfac * T(kk) * scale;
@@ -349,8 +368,9 @@ __device__ __forceinline__ void dx_rows(int nrows, int N, int log2N, T kfac,
 
 // Forward FFT of real rows, packed in pairs, into spec[(nrows+1)/2][N] (global). Barrier at end.
 template <typename T, class LD>
-__device__ void rows_fft_to_global(int nrows, int N, int log2N, gptr<const cpx<T>> __restrict__ tw,
-                                   int fftb, LD ld, gptr<cpx<T>> spec) {
+__device__ void rows_fft_to_global(int nrows, int N, int log2N, int fftb, LD ld,
+                                   gptr<cpx<T>> spec) {
+  const cpx<T>* tw = lds_tw<T>(fftb, N);
   const int npairs = (nrows + 1) >> 1;
   if (fft_by_wave<T>(N, fftb)) {
     const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
@@ -387,8 +407,9 @@ __device__ void rows_fft_to_global(int nrows, int N, int log2N, gptr<const cpx<T
 // Inverse FFT (unscaled) of packed spectra spec[(nrows+1)/2][N]; st(j, i, v) receives the real
 // rows. Barrier at end.
 template <typename T, class ST>
-__device__ void rows_ifft_from_global(int nrows, int N, int log2N, gptr<const cpx<T>> __restrict__ tw,
-                                      int fftb, gptr<const cpx<T>> spec, ST st) {
+__device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
+                                      gptr<const cpx<T>> spec, ST st) {
+  const cpx<T>* tw = lds_tw<T>(fftb, N);
   const int npairs = (nrows + 1) >> 1;
   if (fft_by_wave<T>(N, fftb)) {
     const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
@@ -496,14 +517,13 @@ template <typename T>
 struct Ctx {
   int nx, log2nx, fftb;
   T kfac;
-  gptr<const cpx<T>> tw;
   Geo<T> g;
 };
 
 template <typename T>
 __device__ __forceinline__ Ctx<T> uni(const Ctx<T>& c) {
   Ctx<T> u;
-  u.nx = uni(c.nx); u.log2nx = uni(c.log2nx); u.fftb = uni(c.fftb); u.kfac = uni(c.kfac); u.tw = uni(c.tw);
+  u.nx = uni(c.nx); u.log2nx = uni(c.log2nx); u.fftb = uni(c.fftb); u.kfac = uni(c.kfac);
   u.g.ao = uni(c.g.ao); u.g.bo = uni(c.g.bo); u.g.ido = uni(c.g.ido); u.g.an = uni(c.g.an);
   u.g.bn = uni(c.g.bn); u.g.idn = uni(c.g.idn); u.g.hx = uni(c.g.hx);
   return u;
@@ -686,10 +706,10 @@ __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int m
   const Geo<T> g = c.g;
   col_dsig<T, NZ>(nx, L.Ds, in, t1);
   __syncthreads();
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
              [=](int j, int i) { return in[j * nx + i]; },
              [=](int j, int i, T v) { t2[j * nx + i] = v; });
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
              [=](int j, int i) {
                return t2[j * nx + i] + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i];
              },
@@ -791,10 +811,10 @@ __device__ __forceinline__ void op_apply_T(const Ctx<T>& c, const Lev<T>& L, int
   const Geo<T> g = c.g;
   colT_start<T, NZ>(nx, L.Ds, L.sig, g, in, t1, t2);
   __syncthreads();
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
              [=](int j, int i) { return (j == 0 || j == NZ - 1) ? T(0) : in[j * nx + i]; },
              [=](int j, int i, T v) { t3[j * nx + i] = v; });
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.tw, c.fftb,
+  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
              [=](int j, int i) { return t1[j * nx + i] - t3[j * nx + i]; },
              [=](int j, int i, T v) { out[j * nx + i] = v; });
   colT_finish<T, NZ>(mode, nx, L.Ds, L.sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega);
@@ -863,16 +883,16 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
       }
     } else if (kind == MODE) {
       const gptr<const T> r = xzero ? gptr<const T>(L.f) : gptr<const T>(L.r);
-      rows_fft_to_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb,
+      rows_fft_to_global<T>(NZ, nx, c.log2nx, c.fftb,
                             [=](int j, int i) { return r[j * nx + i]; }, L.spec);
       mode_matvec<T, NZ, TR>(nx, L.modeinv, L.spec);
       __syncthreads();
       const gptr<T> x = L.x;
       if (xzero)
-        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb, L.spec,
+        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.fftb, L.spec,
                                  [=](int j, int i, T v) { x[j * nx + i] = wm * v; });
       else
-        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.tw, c.fftb, L.spec,
+        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.fftb, L.spec,
                                  [=](int j, int i, T v) { x[j * nx + i] += wm * v; });
       xzero = false;
     } else {

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256) k_fill(double* a, int64_t n, double v) {
 
 // ----------------------------------------------------------------------------- geometry kernel
 
-constexpr int kGeoFftBytes = 32768;   // the geometry kernel runs with 2 x 32 KB of FFT LDS
+constexpr int kGeoFftBytes = 32768;   // the geometry kernel: 2 x 32 KB of FFT LDS + twiddles
 //
 // One workgroup per tank: copies h, eta_old, eta_new, checks d > 0, and forms the
 // sigma-metrics of paper eq. 1_Scoef for both geometries: sigma_x = a + b sigma with
@@ -121,9 +121,10 @@ __global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ d
     const double d0 = a + b, d1 = a + c;
     if (!(d0 > 0.0) || !(d1 > 0.0) || !isfinite(d0) || !isfinite(d1)) bad = 1;
   }
-  __syncthreads();
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx,
+                 kGeoFftBytes);
   // rows: 0 = h, 1 = d_old, 2 = d_new  ->  h_x (GEO_HX), d_x old (GEO_BO), d_x new (GEO_BN)
-  dx_rows<double>(3, nx, td.log2nx, td.kfac, gcp<cpx<double>>(ws, td.tw[0]), kGeoFftBytes,
+  dx_rows<double>(3, nx, td.log2nx, td.kfac, kGeoFftBytes,
                   [=](int j, int i) {
                     return j == 0 ? G[GEO_H * nx + i]
                                   : G[GEO_H * nx + i] + G[(j == 1 ? GEO_EO : GEO_EN) * nx + i];
@@ -324,9 +325,9 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
     return;
   }
 
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx, fftb);
   Ctx<double> c64;
   c64.nx = nx; c64.log2nx = td.log2nx; c64.kfac = td.kfac; c64.fftb = fftb;
-  c64.tw = gcp<cpx<double>>(ws, td.tw[0]);
   c64.g = make_geo<double>(ws, td);
   Lev<double> A64 = make_lev<double>(ws, td.lev[0]);
   A64.t1 = gmp<double>(ws, td.a1); A64.t2 = gmp<double>(ws, td.a2);
@@ -335,7 +336,6 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
 
   Ctx<TV> cv;
   cv.nx = nx; cv.log2nx = td.log2nx; cv.kfac = (TV)td.kfac; cv.fftb = fftb;
-  cv.tw = gcp<cpx<TV>>(ws, td.tw[std::is_same<TV, double>::value ? 0 : 1]);
   cv.g = make_geo<TV>(ws, td);
   LevSet<TV> levs{ws, &td, gptr<TV>(nullptr), gptr<TV>(nullptr)};
   Lev<TV> L0 = levs(0);

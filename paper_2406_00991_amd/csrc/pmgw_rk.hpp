@@ -56,14 +56,15 @@ struct RkCoef {
   double a, b, dt, rho, g, nu;
 };
 
-// float64 context of a tank: metrics of the geometry last set, finest-level constants.
+// float64 context of a tank: metrics of the geometry last set, finest-level constants; also
+// stages the tank's twiddles in LDS (a workgroup barrier: every thread must call it).
 __device__ __forceinline__ void rk_ctx(char* ws, const TankDesc& td, int fftb, Ctx<double>& c,
                                        Lev<double>& A) {
   c.nx = td.nx;
   c.log2nx = td.log2nx;
   c.kfac = td.kfac;
   c.fftb = fftb;
-  c.tw = gcp<cpx<double>>(ws, td.tw[0]);
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), td.nx, fftb);
   c.g = make_geo<double>(ws, td);
   A = make_lev<double>(ws, td.lev[0]);
   A.t1 = gmp<double>(ws, td.a1);
@@ -94,9 +95,9 @@ __global__ void __launch_bounds__(256) k_rk_pre(const TankDesc* __restrict__ des
   const gptr<double> eo = as_global(rb.eo + td.off1d);
   const gptr<double> et = as_global(rb.etat + td.off1d);
   const gptr<double> ex = as_global(rb.etax + td.off1d);
-  const gptr<const cpx<double>> tw = gcp<cpx<double>>(ws, td.tw[0]);
   const gptr<const double> fx = gcp<double>(ws, td.filtx);
-  dx_rows<double>(1, nx, td.log2nx, td.kfac, tw, fftb, [=](int, int i) { return e[i]; },
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx, fftb);
+  dx_rows<double>(1, nx, td.log2nx, td.kfac, fftb, [=](int, int i) { return e[i]; },
                   [=](int, int i, double v) { ex[i] = v; });
   for (int i = tid(); i < nx; i += nthr()) {
     const double rate = -u0[i] * ex[i] + w0[i];
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(256) k_rk_pre(const TankDesc* __restrict__ des
     e[i] = e[i] + cf.b * k;
   }
   __syncthreads();
-  spectral_rows<double>(1, nx, td.log2nx, tw, fftb, [=](int, int i) { return e[i]; },
+  spectral_rows<double>(1, nx, td.log2nx, fftb, [=](int, int i) { return e[i]; },
                         [=](int n, cpx<double> v) { return filt_mul(fx, nx, n, v); },
                         [=](int, int i, double v) { e[i] = v; });
 }
@@ -161,7 +162,7 @@ __global__ void __launch_bounds__(256) k_rk_force(const TankDesc* __restrict__ d
   col_dsig<double, NZ>(nx, A.Ds, us, t1);
   col_dsig<double, NZ>(nx, A.Ds, wsv, t3);
   __syncthreads();
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb, [=](int j, int i) { return us[j * nx + i]; },
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb, [=](int j, int i) { return us[j * nx + i]; },
                   [=](int j, int i, double v) { t2[j * nx + i] = v; });
   const double scale = cf.rho / (cf.b * cf.dt);
   for (int e = tid(); e < n; e += nthr()) {
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ de
   const gptr<const double> fz = gcp<double>(ws, td.filtz);
   col_dsig<double, NZ>(nx, A.Ds, pp, t1);
   __syncthreads();
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb, [=](int j, int i) { return pp[j * nx + i]; },
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb, [=](int j, int i) { return pp[j * nx + i]; },
                   [=](int j, int i, double v) { t2[j * nx + i] = v; });
   const double ir = 1.0 / cf.rho;
   for (int e = tid(); e < n; e += nthr()) {
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ de
   for (int comp = 0; comp < 2; ++comp) {
     const gptr<const double> src = comp == 0 ? gptr<const double>(r1) : gptr<const double>(r2);
     const gptr<double> dst = comp == 0 ? uu : wwp;
-    spectral_rows<double>(NZ, nx, c.log2nx, c.tw, fftb,
+    spectral_rows<double>(NZ, nx, c.log2nx, fftb,
                           [=](int j, int i) { return src[j * nx + i]; },
                           [=](int k, cpx<double> v) { return filt_mul(fx, nx, k, v); },
                           [=](int j, int i, double v) { t3[j * nx + i] = v; });

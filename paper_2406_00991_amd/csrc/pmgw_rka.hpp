@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_rka_post(const TankDesc* __restrict__ d
       for (int j = 0; j < NZ; ++j) t3[j * nx + i] = colT<NZ>(fz, col, j);
     }
     __syncthreads();
-    spectral_rows<double>(NZ, nx, c.log2nx, c.tw, fftb,
+    spectral_rows<double>(NZ, nx, c.log2nx, fftb,
                           [=](int j, int i) { return t3[j * nx + i]; },
                           [=](int k, cpx<double> z) { return filt_mul(fx, nx, k, z); },
                           [=](int j, int i, double z) { v[j * nx + i] = z; });
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_rka_post(const TankDesc* __restrict__ d
     hxb[i] = 0.0;
   }
   __syncthreads();
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                   [=](int j, int i) { return gbx[j * nx + i]; },
                   [=](int j, int i, double z) { pb[j * nx + i] -= z; });
 }
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) k_rka_mid(const TankDesc* __restrict__ de
   const double s = cf.rho / (cf.b * cf.dt);
   col_dsig<double, NZ>(nx, Ds, pp, t1);
   __syncthreads();
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                   [=](int j, int i) { return pp[j * nx + i]; },
                   [=](int j, int i, double z) { t2[j * nx + i] = z; });
   for (int i = tid(); i < nx; i += nthr()) {
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(256) k_rka_mid(const TankDesc* __restrict__ de
     }
   }
   __syncthreads();
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                   [=](int j, int i) { return (j == 0 || j == NZ - 1) ? 0.0 : lam[j * nx + i]; },
                   [=](int j, int i, double z) { q3[j * nx + i] = z; });
   for (int i = tid(); i < nx; i += nthr()) {
@@ -342,16 +342,16 @@ __global__ void __launch_bounds__(256) k_rka_force(const TankDesc* __restrict__ 
   }
   __syncthreads();
   // -u D_x u, -u D_x w: ubar += -Fubar D_x u + D_x(u Fubar) - Fwbar D_x w; wbar += D_x(u Fwbar)
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                   [=](int j, int i) { return uu[j * nx + i]; },
                   [=](int j, int i, double z) { t2[j * nx + i] = z; });
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                   [=](int j, int i) { return wwp[j * nx + i]; },
                   [=](int j, int i, double z) { t3[j * nx + i] = z; });
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                   [=](int j, int i) { return uu[j * nx + i] * fub[j * nx + i]; },
                   [=](int j, int i, double z) { q1[j * nx + i] = z; });
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                   [=](int j, int i) { return uu[j * nx + i] * fwb[j * nx + i]; },
                   [=](int j, int i, double z) { q2[j * nx + i] = z; });
   for (int e = tid(); e < n; e += nthr()) {
@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(256) k_rka_force(const TankDesc* __restrict__ 
   }
   // -g D_x eta broadcast over the rows: etabar += g D_x (sum_j Fubar_j)
   const double gg = cf.g;
-  dx_rows<double>(1, nx, c.log2nx, c.kfac, c.tw, fftb, [=](int, int i) { return sfu[i]; },
+  dx_rows<double>(1, nx, c.log2nx, c.kfac, fftb, [=](int, int i) { return sfu[i]; },
                   [=](int, int i, double z) { etabf[i] = gg * z; });
   // nu Div_old Grad_old f for f = u (D_x f in t2) and f = w (D_x f in t3); t1 = D_s f
   const double nu = cf.nu;
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(256) k_rka_force(const TankDesc* __restrict__ 
       }
     }
     __syncthreads();
-    dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+    dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                     [=](int j, int i) { return nu * fb[j * nx + i]; },
                     [=](int j, int i, double z) { q3[j * nx + i] = z; });
     // Gbar_x = q1 - q3, Gbar_z = q2; Grad^T: fbar += -D_x Gbar_x + D_s^T (sx Gbar_x + i Gbar_z)
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(256) k_rka_force(const TankDesc* __restrict__ 
       mo.i[i] += si;
     }
     __syncthreads();
-    dx_rows<double>(NZ, nx, c.log2nx, c.kfac, c.tw, fftb,
+    dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb,
                     [=](int j, int i) { return q1[j * nx + i]; },
                     [=](int j, int i, double z) { outb[j * nx + i] -= z; });
   }
@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(256) k_rka_pre(const TankDesc* __restrict__ de
   }
   __syncthreads();
   // y[r] <- D_x y[r] for r = 0..3
-  dx_rows<double>(4, nx, c.log2nx, c.kfac, c.tw, fftb,
+  dx_rows<double>(4, nx, c.log2nx, c.kfac, fftb,
                   [=](int r, int i) { return y[r * nx + i]; },
                   [=](int r, int i, double z) { y[r * nx + i] = z; });
   // dbar_new (etabar of the new surface) -> row 4; e1bar = F_x (etabar_out + dbar_new) -> row 0
@@ -498,7 +498,7 @@ __global__ void __launch_bounds__(256) k_rka_pre(const TankDesc* __restrict__ de
     y[5 * nx + i] = dbo;
   }
   __syncthreads();
-  spectral_rows<double>(1, nx, c.log2nx, c.tw, fftb,
+  spectral_rows<double>(1, nx, c.log2nx, fftb,
                         [=](int, int i) { return e_b[i] + y[4 * nx + i]; },
                         [=](int k, cpx<double> z) { return filt_mul(fx, nx, k, z); },
                         [=](int, int i, double z) { y[i] = z; });
@@ -513,7 +513,7 @@ __global__ void __launch_bounds__(256) k_rka_pre(const TankDesc* __restrict__ de
     y[nx + i] = u0[i] * etb;
   }
   __syncthreads();
-  dx_rows<double>(1, nx, c.log2nx, c.kfac, c.tw, fftb, [=](int, int i) { return y[nx + i]; },
+  dx_rows<double>(1, nx, c.log2nx, c.kfac, fftb, [=](int, int i) { return y[nx + i]; },
                   [=](int, int i, double z) { y[2 * nx + i] = z; });
   for (int i = tid(); i < nx; i += nthr())
     e_b[i] = y[i] + etabf[i] + y[2 * nx + i] + y[5 * nx + i];

@@ -1,0 +1,76 @@
+"""The 512-tank batch of uneven (Nx, Nz) in one batched solve call (mixed precision), against the
+oracle.
+
+- Every tank: status OK, and the GPU solution's relative residual, evaluated with the ORACLE's
+  operator (the definition), is <= 1.5e-10 when the GPU solves to 1e-10 (the GPU's own stopping
+  test uses its own float64 operator, equal to the oracle's to ~1e-15).
+- Sampled tanks (one per (Nx, Nz) class present, up to 12): delta against the oracle's
+  p-multigrid FGMRES solution at 1e-12 is <= 1e-7 (residual 1e-10 times condition numbers of
+  up to ~1e3 at these sizes).
+"""
+import numpy as np
+import pytest
+
+from oracle import krylov
+from oracle import operator as op
+from oracle import pmg
+from paper_2406_00991_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(tanks, precision="mixed"):
+    import torch
+
+    from paper_2406_00991_amd import pmgw
+    plan = pmgw.Plan([t["nx"] for t in tanks], [t["nz"] for t in tanks],
+                     [t["L"] for t in tanks], precision=precision)
+    cat = lambda key: torch.tensor(np.concatenate([np.asarray(t[key]).ravel() for t in tanks]),
+                                   dtype=torch.float64, device="cuda")
+    plan.set_geometry(cat("h"), cat("eta_old"), cat("eta_new"))
+    return pmgw, plan, cat("b")
+
+
+def test_batch_512_tanks_one_call():
+    tanks = wl.batch(0, 512)
+    pmgw, plan, b = _setup(tanks)
+    p = plan.field()
+    info = pmgw.poisson_solve(plan, b, p, rtol=1e-10, maxit=200)
+    assert all(i[1] == 0 for i in info), [i for i in info if i[1] != 0][:5]
+    assert max(i[2] for i in info) <= 1e-10
+    sols = [a.cpu().numpy() for a in plan.split2d(p)]
+    worst = 0.0
+    for t, x in zip(tanks, sols):
+        g = op.Geometry(t["h"], t["eta_old"], t["L"])
+        worst = max(worst, op.relres(x, t["b"], g, g))
+    assert worst <= 1.5e-10, worst
+    seen = {}
+    for k, t in enumerate(tanks):
+        seen.setdefault((t["nx"], t["nz"]), k)
+    for key, k in sorted(seen.items())[:12]:
+        t = tanks[k]
+        g = op.Geometry(t["h"], t["eta_old"], t["L"])
+        H = pmg.Hierarchy(t["nx"], t["nz"] - 1, g, g, pmg.PmgOptions())
+        ref, inf = krylov.fgmres(lambda v: op.apply(v, g, g), t["b"], H, rtol=1e-12, maxit=300)
+        assert inf["converged"], key
+        d = np.linalg.norm(sols[k] - ref) / np.linalg.norm(ref)
+        assert d <= 1e-7, (key, d)
+
+
+def test_batch_concurrent_classes_match_separate_plans():
+    """A mixed-class batch gives, tank by tank, the same float64 result as one plan per class
+    (the classes run on concurrent streams; each tank's arithmetic is independent of the
+    others)."""
+    tanks = wl.batch(3, 24)
+    pmgw, plan, b = _setup(tanks, "fp64")
+    p = plan.field()
+    pmgw.poisson_solve(plan, b, p, rtol=1e-11, maxit=200)
+    joint = [a.cpu().numpy() for a in plan.split2d(p)]
+    for nz in sorted({t["nz"] for t in tanks}):
+        idx = [k for k, t in enumerate(tanks) if t["nz"] == nz]
+        sub = [tanks[k] for k in idx]
+        pm, pl, bb = _setup(sub, "fp64")
+        q = pl.field()
+        pm.poisson_solve(pl, bb, q, rtol=1e-11, maxit=200)
+        for k, x in zip(idx, pl.split2d(q)):
+            assert np.array_equal(joint[k], x.cpu().numpy())
