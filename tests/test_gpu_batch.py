@@ -5,8 +5,8 @@ oracle.
   operator (the definition), is <= 1.5e-10 when the GPU solves to 1e-10 (the GPU's own stopping
   test uses its own float64 operator, equal to the oracle's to ~1e-15).
 - Sampled tanks (one per (Nx, Nz) class present, up to 12): delta against the oracle's
-  p-multigrid FGMRES solution at 1e-12 is <= 1e-7 (residual 1e-10 times condition numbers of
-  up to ~1e3 at these sizes).
+  p-multigrid FGMRES solution at 5e-12 (above the Nz = 33 rounding floors) is <= 1e-7 (residual
+  1e-10 times condition numbers of up to ~1e3 at these sizes).
 """
 import numpy as np
 import pytest
@@ -51,8 +51,8 @@ def test_batch_512_tanks_one_call():
         t = tanks[k]
         g = op.Geometry(t["h"], t["eta_old"], t["L"])
         H = pmg.Hierarchy(t["nx"], t["nz"] - 1, g, g, pmg.PmgOptions())
-        ref, inf = krylov.fgmres(lambda v: op.apply(v, g, g), t["b"], H, rtol=1e-12, maxit=300)
-        assert inf["converged"], key
+        ref, inf = krylov.fgmres(lambda v: op.apply(v, g, g), t["b"], H, rtol=5e-12, maxit=300)
+        assert inf["relres"] <= 2e-11, key     # Nz = 33 tanks have rounding floors near 1e-12
         d = np.linalg.norm(sols[k] - ref) / np.linalg.norm(ref)
         assert d <= 1e-7, (key, d)
 

@@ -6,11 +6,11 @@ Inputs are the seeded workloads; expected values come from the oracle only. Tole
   numbers reach ~1e6 at Nz = 33, so two correct float64 evaluations differ by ~1e-10), mixed
   plans to 2e-3 (float32 smoothing with Chebyshev second derivatives, whose rounding grows like
   M^4 u);
-- poisson_solve: delta = ||p - p_oracle||/||p_oracle|| <= 1e-12 (float64) and <= 1e-10 (mixed
-  precision after float64 refinement). The stopping tolerance is 1e-12, raised to ten times the
-  case's rounding floor when that is higher: the floor is the relative residual of the oracle's own
-  converged solution, since ||A|| ||p|| u / ||b|| bounds how small any float64 evaluation of
-  b - A p can get (about 4e-13 at 256 x 17, 1e-12 at Nz = 33).
+- poisson_solve: delta = ||p - p_oracle||/||p_oracle|| <= rtol (float64) and <= 1e-10 (mixed
+  precision after float64 refinement), where the stopping tolerance rtol is 1e-12, raised to ten
+  times the case's rounding floor when that is higher: the floor is the relative residual of the
+  oracle's own converged solution, since ||A|| ||p|| u / ||b|| bounds how small any float64
+  evaluation of b - A p can get (about 4e-13 at 256 x 17, 1e-12 at Nz = 33).
 """
 import math
 
@@ -161,7 +161,7 @@ def test_poisson_solve_parity(case, precision):
               f"relres(gpu) {inf[2]:.2e} relres(oracle op) {rr:.2e} delta {delta:.2e}", flush=True)
         assert inf[1] == 0 and inf[2] <= rtol
         assert rr <= 10 * rtol
-        assert delta <= (1e-12 if precision == "fp64" else 1e-10)
+        assert delta <= (rtol if precision == "fp64" else 1e-10)
         if "exact" in pr and pr["name"] == "manufactured":
             assert np.abs(g - pr["exact"]).max() < 1e-9
 
