@@ -63,7 +63,7 @@ typedef struct {
     double filt_fx;         /* x cut-off fraction of Nx/2 [0.5]                               */
     double filt_fz;         /* sigma cut-off fraction of M [0.9]                              */
     int32_t threads;        /* threads per solve workgroup: 64, 128 or 256; 0 = 256 [0]      */
-    int32_t reserved;
+    int32_t adapt_omega_m;  /* 1: scale omega_m per tank by the depth-variation rule below [1]   */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */
@@ -74,6 +74,10 @@ typedef struct {
 } pmgw_info;
 
 typedef struct pmgw_plan_s* pmgw_plan;
+
+/* The depth-variation rule of adapt_omega_m: with c = 1/(d_old d_new) over the tank's columns
+ * and r = max c / min c, omega_m is multiplied by min(1, 2 / (1 + (r/2)^0.4)); it is 1 for flat
+ * and mildly varying depth (r <= 2) and about 0.56 at a depth ratio of 4.6. */
 
 /* Fill *opts with the defaults. */
 void pmgw_default_opts(pmgw_opts* opts);

@@ -230,6 +230,8 @@ KOpts kopts(const pmgw_plan_s* p) {
   o.restart = p->opts.restart;
   o.omega_c = p->opts.omega_c;
   o.omega_m = p->opts.omega_m;
+  o.adapt = p->opts.adapt_omega_m;
+  o.pad = 0;
   return o;
 }
 
@@ -355,6 +357,7 @@ void pmgw_default_opts(pmgw_opts* o) {
   o->filt_fx = 0.5;
   o->filt_fz = 0.9;
   o->threads = 0;
+  o->adapt_omega_m = 1;
 }
 
 const char* pmgw_last_error(void) { return g_err.c_str(); }
@@ -384,6 +387,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     return fail(PMGW_EINVAL, "damping factors must be in (0, 2)");
   if (o.threads != 0 && o.threads != 64 && o.threads != 128 && o.threads != 256)
     return fail(PMGW_EINVAL, "threads must be 0, 64, 128 or 256");
+  if (o.adapt_omega_m != 0 && o.adapt_omega_m != 1)
+    return fail(PMGW_EINVAL, "adapt_omega_m must be 0 or 1");
   for (int t = 0; t < ntanks; ++t) {
     const int n = nx[t], M = nz[t] - 1;
     if (n < 8 || n > 2048 || (n & (n - 1)) != 0)

@@ -89,6 +89,18 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Maximum over the workgroup; every thread returns the same value.
+__device__ __forceinline__ double block_max(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int lane = tid() & 63, wid = tid() >> 6, nw = nthr() >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int i = 1; i < nw; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
 // ----------------------------------------------------------------------------- FFT in LDS
 //
 // Stockham auto-sort FFT of `nrows` complex rows of length N = 2^log2N held in LDS buffer a
@@ -188,66 +200,97 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The Stockham FFT of fft_lds for ONE row of length N (64 <= N <= 512) owned by one wavefront,
-// in place: each pass reads its inputs into registers (at most 8 complex values per lane),
-// synchronises the wavefront, and writes its outputs over them.
-template <typename T, bool INV>
-__device__ void fft_wave(cpx<T>* a, int N, int log2N, const cpx<T>* __restrict__ tw, int lane) {
-  cpx<T> r[8];
+// The Stockham FFT of fft_lds for nr <= RM rows at a, a + N, ..., a + (nr-1) N of length N
+// (64 <= N <= 512), owned by one wavefront and done in place: each radix pass reads the inputs
+// of all rows before one wavefront sync and writes all outputs before the next, so the rows' LDS
+// and arithmetic latencies overlap; the twiddles of a butterfly are read once for all rows.
+template <typename T, bool INV, int RM>
+__device__ void fft_wave_m(cpx<T>* a, int nr, int N, int log2N, const cpx<T>* __restrict__ tw,
+                           int lane) {
   int p = 1;
   if (log2N & 1) {
     const int h = N >> 1;
+    cpx<T> r[RM][8];
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int i = lane + 64 * it;
-      if (i < h) { r[2 * it] = a[i]; r[2 * it + 1] = a[i + h]; }
+    for (int q = 0; q < RM; ++q) {
+      if (q < nr) {
+        const cpx<T>* s = a + q * N;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int i = lane + 64 * it;
+          if (i < h) { r[q][2 * it] = s[i]; r[q][2 * it + 1] = s[i + h]; }
+        }
+      }
     }
     wave_sync();
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int i = lane + 64 * it;
-      if (i < h) {
-        a[2 * i] = cadd(r[2 * it], r[2 * it + 1]);
-        a[2 * i + 1] = csub(r[2 * it], r[2 * it + 1]);
+    for (int q = 0; q < RM; ++q) {
+      if (q < nr) {
+        cpx<T>* d = a + q * N;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int i = lane + 64 * it;
+          if (i < h) {
+            d[2 * i] = cadd(r[q][2 * it], r[q][2 * it + 1]);
+            d[2 * i + 1] = csub(r[q][2 * it], r[q][2 * it + 1]);
+          }
+        }
       }
     }
     wave_sync();
     p = 2;
   }
   while (p < N) {
-    const int q = N >> 2;
+    const int qn = N >> 2;
     const int tstep = N / (4 * p);
+    cpx<T> r[RM][8];
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int i = lane + 64 * it;
-      if (i < q) {
-        r[4 * it] = a[i]; r[4 * it + 1] = a[i + q];
-        r[4 * it + 2] = a[i + 2 * q]; r[4 * it + 3] = a[i + 3 * q];
+    for (int q = 0; q < RM; ++q) {
+      if (q < nr) {
+        const cpx<T>* s = a + q * N;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+          const int i = lane + 64 * it;
+          if (i < qn) {
+            r[q][4 * it] = s[i]; r[q][4 * it + 1] = s[i + qn];
+            r[q][4 * it + 2] = s[i + 2 * qn]; r[q][4 * it + 3] = s[i + 3 * qn];
+          }
+        }
       }
     }
     wave_sync();
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
       const int i = lane + 64 * it;
-      if (i < q) {
+      if (i < qn) {
         const int k = i & (p - 1);
-        cpx<T> u0 = r[4 * it], u1 = r[4 * it + 1], u2 = r[4 * it + 2], u3 = r[4 * it + 3];
+        cpx<T> w1 = {T(1), T(0)}, w2 = w1, w3 = w1;
         if (p > 1) {
           const int t = k * tstep;
-          cpx<T> w1 = tw[t], w2 = tw[2 * t], w3 = tw[3 * t];
+          w1 = tw[t]; w2 = tw[2 * t]; w3 = tw[3 * t];
           if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
-          u1 = cmul(u1, w1);
-          u2 = cmul(u2, w2);
-          u3 = cmul(u3, w3);
         }
-        const cpx<T> v0 = cadd(u0, u2), v1 = csub(u0, u2), v2 = cadd(u1, u3);
-        const cpx<T> dd = csub(u1, u3);
-        const cpx<T> v3 = INV ? cpx<T>{-dd.im, dd.re} : cpx<T>{dd.im, -dd.re};
         const int j = ((i - k) << 2) + k;
-        a[j] = cadd(v0, v2);
-        a[j + p] = cadd(v1, v3);
-        a[j + 2 * p] = csub(v0, v2);
-        a[j + 3 * p] = csub(v1, v3);
+#pragma unroll
+        for (int q = 0; q < RM; ++q) {
+          if (q < nr) {
+            cpx<T> u0 = r[q][4 * it], u1 = r[q][4 * it + 1], u2 = r[q][4 * it + 2];
+            cpx<T> u3 = r[q][4 * it + 3];
+            if (p > 1) {
+              u1 = cmul(u1, w1);
+              u2 = cmul(u2, w2);
+              u3 = cmul(u3, w3);
+            }
+            const cpx<T> v0 = cadd(u0, u2), v1 = csub(u0, u2), v2 = cadd(u1, u3);
+            const cpx<T> dd = csub(u1, u3);
+            const cpx<T> v3 = INV ? cpx<T>{-dd.im, dd.re} : cpx<T>{dd.im, -dd.re};
+            cpx<T>* d = a + q * N;
+            d[j] = cadd(v0, v2);
+            d[j + p] = cadd(v1, v3);
+            d[j + 2 * p] = csub(v0, v2);
+            d[j + 3 * p] = csub(v1, v3);
+          }
+        }
       }
     }
     wave_sync();
@@ -255,40 +298,75 @@ __device__ void fft_wave(cpx<T>* a, int N, int log2N, const cpx<T>* __restrict__
   }
 }
 
-// Load the packed row pair (ra, ra+1) of length N <= 512 into the wavefront's LDS row: all
+// Rows of the multi-row wavefront FFT: at most kWaveRows row pairs per wavefront and round.
+constexpr int kWaveRows = 3;
+
+// Row pairs per wavefront and round for the wavefront FFT (bounded by kWaveRows, by what the
+// FFT buffer holds, and by the work: npairs spread over the wavefronts).
+template <typename T>
+__device__ __forceinline__ int wave_rows(int N, int fftb, int npairs) {
+  const int nw = nthr() >> 6;
+  const int fit = (2 * fft_cap<T>(fftb)) / (nw * N);
+  const int need = (npairs + nw - 1) / nw;
+  return max(1, min(kWaveRows, min(fit, need)));
+}
+
+// Load row pairs pp0, pp0 + nw, ... (nr of them) as packed complex rows into A, A + N, ...: all
 // global loads are issued before the first LDS write.
 template <typename T, class LD>
-__device__ __forceinline__ void wave_load_pair(cpx<T>* A, int N, int lane, int ra, int nrows,
-                                               LD ld) {
-  cpx<T> v[8];
+__device__ __forceinline__ void wave_load_pairs(cpx<T>* A, int nr, int N, int lane, int pp0,
+                                                int nw, int nrows, LD ld) {
+  cpx<T> v[kWaveRows][8];
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int n = lane + 64 * it;
-    if (n < N) v[it] = {ld(ra, n), (ra + 1 < nrows) ? ld(ra + 1, n) : T(0)};
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+      const int ra = 2 * (pp0 + q * nw);
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) v[q][it] = {ld(ra, n), (ra + 1 < nrows) ? ld(ra + 1, n) : T(0)};
+      }
+    }
   }
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int n = lane + 64 * it;
-    if (n < N) A[n] = v[it];
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) A[q * N + n] = v[q][it];
+      }
+    }
   }
 }
 
-// Hand the wavefront's LDS row back as the real rows (ra, ra+1): LDS reads first, then st().
+// Hand the wavefront's LDS rows back as real row pairs: LDS reads first, then st().
 template <typename T, class ST>
-__device__ __forceinline__ void wave_store_pair(const cpx<T>* A, int N, int lane, int ra,
-                                                int nrows, ST st) {
-  cpx<T> v[8];
+__device__ __forceinline__ void wave_store_pairs(const cpx<T>* A, int nr, int N, int lane,
+                                                 int pp0, int nw, int nrows, ST st) {
+  cpx<T> v[kWaveRows][8];
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int n = lane + 64 * it;
-    if (n < N) v[it] = A[n];
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) v[q][it] = A[q * N + n];
+      }
+    }
   }
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int n = lane + 64 * it;
-    if (n < N) {
-      st(ra, n, v[it].re);
-      if (ra + 1 < nrows) st(ra + 1, n, v[it].im);
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+      const int ra = 2 * (pp0 + q * nw);
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) {
+          st(ra, n, v[q][it].re);
+          if (ra + 1 < nrows) st(ra + 1, n, v[q][it].im);
+        }
+      }
     }
   }
 }
@@ -310,16 +388,19 @@ __device__ void spectral_rows(int nrows, int N, int log2N, int fftb, LD ld, SM s
   const cpx<T>* tw = lds_tw<T>(fftb, N);
   if (fft_by_wave<T>(N, fftb)) {
     const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
-    cpx<T>* A = fft_buf<T>() + w * N;
-    for (int pp = w; pp < npairs; pp += nw) {
-      const int ra = 2 * pp;
-      wave_load_pair<T>(A, N, lane, ra, nrows, ld);
+    const int R = wave_rows<T>(N, fftb, npairs);
+    cpx<T>* A = fft_buf<T>() + w * R * N;
+    for (int base = 0; base < npairs; base += nw * R) {
+      const int pp0 = base + w;
+      const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
+      wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
       wave_sync();
-      fft_wave<T, false>(A, N, log2N, tw, lane);
-      for (int n = lane; n < N; n += 64) A[n] = sm(n, A[n]);
+      fft_wave_m<T, false, kWaveRows>(A, nr, N, log2N, tw, lane);
+      for (int q = 0; q < nr; ++q)
+        for (int n = lane; n < N; n += 64) A[q * N + n] = sm(n, A[q * N + n]);
       wave_sync();
-      fft_wave<T, true>(A, N, log2N, tw, lane);
-      wave_store_pair<T>(A, N, lane, ra, nrows, st);
+      fft_wave_m<T, true, kWaveRows>(A, nr, N, log2N, tw, lane);
+      wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
       wave_sync();
     }
     __syncthreads();
@@ -374,13 +455,16 @@ __device__ void rows_fft_to_global(int nrows, int N, int log2N, int fftb, LD ld,
   const int npairs = (nrows + 1) >> 1;
   if (fft_by_wave<T>(N, fftb)) {
     const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
-    cpx<T>* A = fft_buf<T>() + w * N;
-    for (int pp = w; pp < npairs; pp += nw) {
-      const int ra = 2 * pp;
-      wave_load_pair<T>(A, N, lane, ra, nrows, ld);
+    const int R = wave_rows<T>(N, fftb, npairs);
+    cpx<T>* A = fft_buf<T>() + w * R * N;
+    for (int base = 0; base < npairs; base += nw * R) {
+      const int pp0 = base + w;
+      const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
+      wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
       wave_sync();
-      fft_wave<T, false>(A, N, log2N, tw, lane);
-      for (int n = lane; n < N; n += 64) gst<T>(spec, pp * N + n, A[n]);
+      fft_wave_m<T, false, kWaveRows>(A, nr, N, log2N, tw, lane);
+      for (int q = 0; q < nr; ++q)
+        for (int n = lane; n < N; n += 64) gst<T>(spec, (pp0 + q * nw) * N + n, A[q * N + n]);
       wave_sync();
     }
     __syncthreads();
@@ -413,25 +497,37 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
   const int npairs = (nrows + 1) >> 1;
   if (fft_by_wave<T>(N, fftb)) {
     const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
-    cpx<T>* A = fft_buf<T>() + w * N;
-    for (int pp = w; pp < npairs; pp += nw) {
-      const int ra = 2 * pp;
+    const int R = wave_rows<T>(N, fftb, npairs);
+    cpx<T>* A = fft_buf<T>() + w * R * N;
+    for (int base = 0; base < npairs; base += nw * R) {
+      const int pp0 = base + w;
+      const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
       {
-        cpx<T> v[8];
+        cpx<T> v[kWaveRows][8];
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          const int n = lane + 64 * it;
-          if (n < N) v[it] = gld<T>(spec, pp * N + n);
+        for (int q = 0; q < kWaveRows; ++q) {
+          if (q < nr) {
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+              const int n = lane + 64 * it;
+              if (n < N) v[q][it] = gld<T>(spec, (pp0 + q * nw) * N + n);
+            }
+          }
         }
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          const int n = lane + 64 * it;
-          if (n < N) A[n] = v[it];
+        for (int q = 0; q < kWaveRows; ++q) {
+          if (q < nr) {
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+              const int n = lane + 64 * it;
+              if (n < N) A[q * N + n] = v[q][it];
+            }
+          }
         }
       }
       wave_sync();
-      fft_wave<T, true>(A, N, log2N, tw, lane);
-      wave_store_pair<T>(A, N, lane, ra, nrows, st);
+      fft_wave_m<T, true, kWaveRows>(A, nr, N, log2N, tw, lane);
+      wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
       wave_sync();
     }
     __syncthreads();

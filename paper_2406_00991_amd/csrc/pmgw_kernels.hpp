@@ -99,7 +99,8 @@ constexpr int kGeoFftBytes = 32768;   // the geometry kernel: 2 x 32 KB of FFT L
 // One workgroup per tank: copies h, eta_old, eta_new, checks d > 0, and forms the
 // sigma-metrics of paper eq. 1_Scoef for both geometries: sigma_x = a + b sigma with
 // a = h_x / d, b = -d_x / d, and 1/d; h_x and d_x by the FFT derivative. Also the x-averages
-// cbar = <1/(d_o d_n)> and ebar = <(1 + h_x^2)/d_o> of the flat-mode operator, and float32
+// cbar = <1/(d_o d_n)> and ebar = <(1 + h_x^2)/d_o> of the flat-mode operator, the mode-step
+// damping factor min(1, 2 / (1 + (r/2)^0.4)) with r = max c / min c, c = 1/(d_o d_n), and float32
 // copies for mixed plans.
 __global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ descs, char* ws,
                                                   const double* h, const double* eo,
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ d
                   [=](int j, int i, double v) {
                     G[(j == 0 ? GEO_HX : (j == 1 ? GEO_BO : GEO_BN)) * nx + i] = v;
                   });
-  double sc = 0.0, se = 0.0;
+  double sc = 0.0, se = 0.0, cmax = 0.0, icmax = 0.0;
   float* G32 = mp<float>(ws, td.geo32);
   for (int i = tid(); i < nx; i += nthr()) {
     const double hx = G[GEO_HX * nx + i];
@@ -147,15 +148,22 @@ __global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ d
     G32[6 * nx + i] = (float)hx;
     sc += ido * idn;
     se += (1.0 + hx * hx) * ido;
+    cmax = fmax(cmax, fabs(ido * idn));
+    icmax = fmax(icmax, 1.0 / fabs(ido * idn));
   }
   sc = block_sum(sc, red);
   se = block_sum(se, red);
+  cmax = block_max(cmax, red);
+  icmax = block_max(icmax, red);
   const double nb = block_sum((double)bad, red);
   if (tid() == 0) {
     double* S = mp<double>(ws, td.scal);
     S[0] = sc / nx;
     S[1] = se / nx;
     *reinterpret_cast<int32_t*>(S + 2) = nb > 0.0 ? ST_EGEOM : ST_OK;
+    // mode-step damping: r = max c / min c with c = 1/(d_o d_n); min(1, 2 / (1 + (r/2)^0.4))
+    const double r = cmax * icmax;
+    S[3] = fmin(1.0, 2.0 / (1.0 + pow(0.5 * r, 0.4)));
   }
 }
 
@@ -326,6 +334,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
   }
 
   stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx, fftb);
+  if (o.adapt) o.omega_m *= cp<double>(ws, td.scal)[3];
   Ctx<double> c64;
   c64.nx = nx; c64.log2nx = td.log2nx; c64.kfac = td.kfac; c64.fftb = fftb;
   c64.g = make_geo<double>(ws, td);

@@ -38,7 +38,8 @@ struct TankDesc {
   int64_t filtz;                    // sigma-filter matrix [nz][nz] on the finest level (float64)
   int64_t geo64;                    // 10 x nx doubles (see GEO_* below)
   int64_t geo32;                    // 7 x nx floats: ao, bo, ido, an, bn, idn, hx
-  int64_t scal;                     // 64 bytes: double cbar, ebar; int32 status at +16
+  int64_t scal;                     // 64 bytes: double cbar, ebar; int32 status at +16;
+                                    // double mode-damping factor at +24
   int64_t V, Z;                     // FGMRES bases: (restart+1) x n and restart x n doubles
   int64_t a1, a2, a3, aspec;        // float64 operator temporaries (finest level)
   LevelDesc lev[kMaxLev];
@@ -57,6 +58,7 @@ struct BlockJob {
 struct KOpts {
   int32_t nu1, nu2, coarse_pairs, restart;
   double omega_c, omega_m;
+  int32_t adapt, pad;               // adapt: scale omega_m by the tank's factor (scal + 24)
 };
 
 }  // namespace pmgw

@@ -33,7 +33,7 @@ class Opts(ctypes.Structure):
                 ("rho", ctypes.c_double), ("g", ctypes.c_double), ("nu_visc", ctypes.c_double),
                 ("filt_alpha", ctypes.c_double), ("filt_s", ctypes.c_double),
                 ("filt_fx", ctypes.c_double), ("filt_fz", ctypes.c_double),
-                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("adapt_omega_m", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

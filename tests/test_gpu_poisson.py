@@ -212,3 +212,22 @@ def test_error_codes():
     assert info[0][1] == pmgw.NOCONV and info[0][0] == 1
     with pytest.raises(pmgw.PmgwError):
         plan.solve(b, rtol=-1.0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_bar_1024x33_solve(seed):
+    """The trapezoidal bar (depth 0.4 to 0.1, slopes 1:20 and 1:10), mixed precision, to 1e-10
+    with the default depth-adapted mode damping: the GPU solution's residual under the oracle's
+    operator is <= 1.5e-10, and it is within 1e-7 of the oracle's own p-multigrid FGMRES
+    solution (stopped at 5e-12, above the Nz = 33 rounding floor)."""
+    pr = wl.bar(seed, 1024, 33)
+    plan = make_plan([pr], "mixed")
+    p, info = plan.solve(upload2d([pr], "b"), rtol=1e-10, maxit=200)
+    assert info[0][1] == 0, info
+    got = download(plan, p)[0]
+    go, gn = geoms(pr)
+    assert op.relres(got, pr["b"], go, gn) <= 1.5e-10
+    H = pmg.Hierarchy(pr["nx"], pr["nz"] - 1, go, gn, pmg.PmgOptions())
+    ref, inf = krylov.fgmres(lambda v: op.apply(v, go, gn), pr["b"], H, rtol=5e-12, maxit=300)
+    assert inf["relres"] <= 2e-11
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-7
