@@ -165,16 +165,17 @@ def run_precision(wave, precision, steps, warmup, rtol):
                 p=T.p.cpu().numpy())
 
 
-def run_batch(seed, ntanks, reps, rtol):
+def run_batch(seed, ntanks, reps, rtol, threads=0):
     """The batched workload: ntanks tanks of uneven (Nx, Nz), first-stage problems, one mixed
-    plan; `reps` timed batched solves (one poisson_solve call each, zero initial guess)."""
+    plan; `reps` timed batched solves (one poisson_solve call each, zero initial guess).
+    threads: workgroup size of the solve kernels (0 = the library default)."""
     import torch
 
     from paper_2406_00991_amd import pmgw
     from paper_2406_00991_amd import workloads as wl
     tanks = wl.batch(seed, ntanks)
     plan = pmgw.Plan([t["nx"] for t in tanks], [t["nz"] for t in tanks], [t["L"] for t in tanks],
-                     precision="mixed")
+                     precision="mixed", opts=pmgw.default_opts(threads=threads))
     cat = lambda key: torch.tensor(np.concatenate([np.asarray(t[key]).ravel() for t in tanks]),
                                    dtype=torch.float64, device="cuda")
     plan.set_geometry(cat("h"), cat("eta_old"), cat("eta_new"))
@@ -199,7 +200,7 @@ def run_batch(seed, ntanks, reps, rtol):
             "value": ntanks * reps / wall, "unit": "tank-solves/s",
             "mean_batch_ms": tot_ms / max(launches, 1), "points": int(sum(t["nx"] * t["nz"] for t in tanks)),
             "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
-            "status": sorted({i[1] for i in info}),
+            "status": sorted({i[1] for i in info}), "threads": threads,
             "roofline": {"bound": "hbm", "achieved": byts / t_launch / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": byts / t_launch / 1e9 / HBM_PEAK_GBS,
                          "alg_bytes_per_batch": byts}}

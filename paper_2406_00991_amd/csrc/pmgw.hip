@@ -244,6 +244,18 @@ int nz_class(int nz) { return nz == 3 ? 0 : nz == 5 ? 1 : nz == 9 ? 2 : nz == 17
 // Largest workgroup the solve kernel is compiled for (its register budget follows from it).
 constexpr int kSolveMaxThreads = 256;
 
+// Bytes of one FFT half for a solve launch. Classes whose rows all go through the wavefront FFT
+// (64 <= Nx <= 512) get what kWaveRows row pairs per wavefront need (2 fftb = wavefronts x
+// kWaveRows x Nx complex float64), so that with fewer threads per workgroup two workgroups fit in
+// one CU's LDS; other classes get 32 KB halves for the workgroup-wide FFT.
+int solve_fftb(int threads, int maxnx) {
+  if (maxnx >= 64 && maxnx <= 512) {
+    const int need = (threads / 64) * kWaveRows * maxnx * 16 / 2;
+    return std::max(4096, std::min(32768, need));
+  }
+  return 32768;
+}
+
 template <typename TV, int NZ, bool TR>
 void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, double rtol,
                   int maxit, pmgw_info_dev* info, const KOpts& o, hipStream_t st) {
@@ -252,8 +264,7 @@ void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, d
   const int nt = (int)p->ids[c].size();
   constexpr int MAXT = kSolveMaxThreads;
   const int thr = p->opts.threads ? p->opts.threads : MAXT;
-  // Two halves of 32 KB of FFT LDS per workgroup: two workgroups fit on one CU.
-  const int fftb = 32768;
+  const int fftb = solve_fftb(thr, p->maxnx[c]);
   hipLaunchKernelGGL((k_solve<TV, NZ, MAXT, TR>), dim3((unsigned)nt), dim3(thr),
                      lds_bytes(fftb, p->maxnx[c]), st, d, ids, p->ws, mode, in, out, rtol, maxit,
                      info, o, fftb);
