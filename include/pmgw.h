@@ -47,6 +47,10 @@ enum {
 
 enum { PMGW_FP64 = 0, PMGW_MIXED = 1 };
 
+/* Preconditioner of poisson_solve: one V-cycle (paper Alg. 1) or one full-multigrid cycle
+ * (paper Alg. 2) per FGMRES iteration. */
+enum { PMGW_CYCLE_V = 0, PMGW_CYCLE_FMG = 1 };
+
 /* Solver and model options. pmgw_default_opts fills the defaults given in brackets. */
 typedef struct {
     int32_t nu1;            /* pre-smoothing pairs per level [1]                              */
@@ -64,6 +68,8 @@ typedef struct {
     double filt_fz;         /* sigma cut-off fraction of M [0.9]                              */
     int32_t threads;        /* threads per solve workgroup: 64, 128 or 256; 0 = 256 [0]      */
     int32_t adapt_omega_m;  /* 1: scale omega_m per tank by the depth-variation rule below [1]   */
+    int32_t cycle;          /* FGMRES preconditioner: PMGW_CYCLE_V or PMGW_CYCLE_FMG [V]       */
+    int32_t reserved;       /* must be 0                                                       */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */
@@ -131,6 +137,14 @@ int laplacian_apply(pmgw_plan plan, const double* p, double* Ap);
  * fields and must not overlap.
  */
 int pmg_vcycle(pmgw_plan plan, const double* r, double* z);
+
+/*
+ * z = one full-multigrid cycle applied to r (paper Alg. 2): the right-hand side restricted to
+ * every level; on the coarsest level the coarse cycle from zero; on each finer level the
+ * prolongated result u of the level below, improved by one V-cycle of that level started from
+ * u (evaluated as u + V_0(f - A u), V_0 the cycle from zero). Same conventions as pmg_vcycle.
+ */
+int pmgw_fmg(pmgw_plan plan, const double* r, double* z);
 
 /*
  * Solve A p = b for every tank with flexible GMRES right-preconditioned by one V-cycle per

@@ -42,6 +42,7 @@ class PmgOptions:
     coarse_pairs: int = 2
     coarse: str = "smooth"        # "smooth" (fixed pairs) or "exact" (dense LU)
     adapt_omega_m: bool = True    # scale omega_m by mode_damping(geometry)
+    cycle: str = "V"              # preconditioner: "V" (Alg. 1) or "FMG" (Alg. 2)
 
 
 def mode_damping(g_old, g_new):
@@ -176,10 +177,11 @@ class Hierarchy:
         self.R = [restriction_matrix(m) for m in self.orders[:-1]]
         self.P = [prolongation_matrix(m) for m in self.orders[:-1]]
 
-    def vcycle(self, f, l=0):
+    def vcycle(self, f, l=0, x0=None):
+        """Alg. 1 on level l from the initial guess x0 (zero when None)."""
         o = self.opts
         lev = self.levels[l]
-        x = np.zeros_like(f)
+        x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.result_type(f, x0))
         if l == len(self.levels) - 1:
             if o.coarse == "exact":
                 return lev.exact(f)
@@ -195,5 +197,21 @@ class Hierarchy:
             x = lev.pair(x, f, o)
         return x
 
+    def fmg(self, f):
+        """Alg. 2: from the coarsest level up, a V-cycle on each level started from the
+        prolongated result of the level below (zero on the coarsest level), the last one on the
+        finest level. The paper leaves the coarser right-hand sides implicit; here each is the
+        restriction R of the next finer one."""
+        fs = [np.asarray(f)]
+        for l in range(len(self.levels) - 1):
+            fs.append(self.R[l] @ fs[-1])
+        u = None
+        for l in range(len(self.levels) - 1, 0, -1):
+            u = self.vcycle(fs[l], l, x0=u)
+            u = self.P[l - 1] @ u
+        return self.vcycle(fs[0], 0, x0=u)
+
     def __call__(self, f):
+        if self.opts.cycle == "FMG":
+            return self.fmg(np.asarray(f))
         return self.vcycle(np.asarray(f))

@@ -231,7 +231,7 @@ KOpts kopts(const pmgw_plan_s* p) {
   o.omega_c = p->opts.omega_c;
   o.omega_m = p->opts.omega_m;
   o.adapt = p->opts.adapt_omega_m;
-  o.pad = 0;
+  o.cycle = p->opts.cycle;
   return o;
 }
 
@@ -369,6 +369,7 @@ void pmgw_default_opts(pmgw_opts* o) {
   o->filt_fz = 0.9;
   o->threads = 0;
   o->adapt_omega_m = 1;
+  o->cycle = PMGW_CYCLE_V;
 }
 
 const char* pmgw_last_error(void) { return g_err.c_str(); }
@@ -400,6 +401,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     return fail(PMGW_EINVAL, "threads must be 0, 64, 128 or 256");
   if (o.adapt_omega_m != 0 && o.adapt_omega_m != 1)
     return fail(PMGW_EINVAL, "adapt_omega_m must be 0 or 1");
+  if (o.cycle != PMGW_CYCLE_V && o.cycle != PMGW_CYCLE_FMG)
+    return fail(PMGW_EINVAL, "cycle must be PMGW_CYCLE_V or PMGW_CYCLE_FMG");
   for (int t = 0; t < ntanks; ++t) {
     const int n = nx[t], M = nz[t] - 1;
     if (n < 8 || n > 2048 || (n & (n - 1)) != 0)
@@ -513,6 +516,7 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
       lv.colinv = cur; cur = align256(cur + vb * (int64_t)lv.nz * lv.nz * d.nx);
       lv.modeinv = cur; cur = align256(cur + vb * (int64_t)lv.nz * lv.nz * (d.nx / 2 + 1));
       lv.x = cur; cur = align256(cur + vb * nl);
+      lv.u = cur; cur = align256(cur + vb * nl);
       lv.f = cur; cur = align256(cur + vb * nl);
       lv.r = cur; cur = align256(cur + vb * nl);
       lv.t1 = cur; cur = align256(cur + vb * nl);
@@ -707,6 +711,16 @@ int poisson_solve(pmgw_plan p, const double* b, double* x, double rtol, int32_t 
                   pmgw_info* info_host, pmgw_info* info_dev) {
   g_err.clear();
   return solve_entry(p, false, b, x, rtol, maxit, info_host, info_dev);
+}
+
+int pmgw_fmg(pmgw_plan p, const double* r, double* z) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!p->geometry_set) return fail(PMGW_EINVAL, "geometry not set");
+  if (!r || !z) return fail(PMGW_EINVAL, "r and z must be non-NULL");
+  if (r == z) return fail(PMGW_EINVAL, "r and z must not overlap");
+  return launch_solve(p, MODE_FMG, r, z, 0.0, 0, nullptr);
 }
 
 int pmgw_adjoint_apply(pmgw_plan p, const double* lam, double* out) {

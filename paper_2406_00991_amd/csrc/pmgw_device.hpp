@@ -605,7 +605,7 @@ struct Lev {
   int nz, nzc;
   gptr<const T> Ds, sig, colinv, modeinv, R, P;
   gptr<const T> PT, RT;          // P^T [nzc][nz] and R^T [nz][nzc] (transposed V-cycle)
-  gptr<T> x, f, r, t1, t2, t3;
+  gptr<T> x, f, r, t1, t2, t3, u;
   gptr<cpx<T>> spec;
 };
 
@@ -632,7 +632,7 @@ __device__ __forceinline__ Lev<T> uni(const Lev<T>& L) {
   u.Ds = uni(L.Ds); u.sig = uni(L.sig); u.colinv = uni(L.colinv); u.modeinv = uni(L.modeinv);
   u.R = uni(L.R); u.P = uni(L.P); u.PT = uni(L.PT); u.RT = uni(L.RT);
   u.x = uni(L.x); u.f = uni(L.f); u.r = uni(L.r); u.t1 = uni(L.t1); u.t2 = uni(L.t2);
-  u.t3 = uni(L.t3); u.spec = uni(L.spec);
+  u.t3 = uni(L.t3); u.u = uni(L.u); u.spec = uni(L.spec);
   return u;
 }
 
@@ -955,6 +955,7 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   KOpts o;
   o.nu1 = uni(o_.nu1); o.nu2 = uni(o_.nu2); o.coarse_pairs = uni(o_.coarse_pairs);
   o.restart = uni(o_.restart); o.omega_c = uni(o_.omega_c); o.omega_m = uni(o_.omega_m);
+  o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle);
   const int nx = c.nx;
   const T wc = T(o.omega_c), wm = T(o.omega_m);
   const Lev<T> L = uni(lev(l));
@@ -1008,6 +1009,45 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   }
   if (xzero) {
     fill_zero(L.x, NZ * nx);
+    __syncthreads();
+  }
+}
+
+// Full multigrid (paper Alg. 2) on the levels l, l+1, ...: input lev(l).f, output lev(l).x.
+// The right-hand side is restricted to the next level and solved there by full multigrid; its
+// result, prolongated, is the initial guess u of this level's V-cycle, evaluated as
+// u + V_0(f - A u) with the V-cycle from zero (the same linear map: every smoothing and
+// correction step commutes with shifting the iterate by u). lev(l).f is overwritten by the
+// residual and lev(l).u holds u. On the coarsest level (3 rows) it is the coarse V-cycle.
+template <typename T, int NZ, class LP>
+__device__ __noinline__ void fmg(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
+  const Ctx<T> c = uni(c_);
+  const LP lev = uni(lev_);
+  const int l = uni(l_);
+  KOpts o;
+  o.nu1 = uni(o_.nu1); o.nu2 = uni(o_.nu2); o.coarse_pairs = uni(o_.coarse_pairs);
+  o.restart = uni(o_.restart); o.omega_c = uni(o_.omega_c); o.omega_m = uni(o_.omega_m);
+  o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle);
+  if constexpr (NZ == 3) {
+    vcycle<T, NZ, LP, false>(c, lev, l, o);
+  } else {
+    constexpr int NZC = (NZ + 1) / 2;
+    const int nx = c.nx;
+    const Lev<T> L = uni(lev(l));
+    const Lev<T> C = uni(lev(l + 1));
+    col_restrict<T, NZ>(nx, L.R, gptr<const T>(L.f), C.f);
+    __syncthreads();
+    fmg<T, NZC>(c, lev, l + 1, o);
+    fill_zero(L.u, NZ * nx);
+    __syncthreads();
+    col_prolong_add<T, NZ>(nx, L.P, gptr<const T>(C.x), L.u);
+    __syncthreads();
+    op_apply<T, NZ>(c, L, FIN_RESID, gptr<const T>(L.u), L.f, gptr<const T>(L.f), gptr<T>(nullptr),
+                    T(0));
+    vcycle<T, NZ, LP, false>(c, lev, l, o);
+    const gptr<T> x = L.x;
+    const gptr<const T> u = L.u;
+    for (int e = tid(); e < NZ * nx; e += nthr()) x[e] += u[e];
     __syncthreads();
   }
 }

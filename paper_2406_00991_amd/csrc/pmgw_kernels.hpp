@@ -11,7 +11,7 @@ struct pmgw_info_dev {
 
 namespace pmgw {
 
-enum : int { MODE_APPLY = 0, MODE_VCYCLE = 1, MODE_SOLVE = 2 };
+enum : int { MODE_APPLY = 0, MODE_VCYCLE = 1, MODE_SOLVE = 2, MODE_FMG = 3 };
 enum : int { ST_OK = 0, ST_NOCONV = 1, ST_EGEOM = -2, ST_ENAN = -3 };
 
 template <typename T>
@@ -61,6 +61,7 @@ __device__ Lev<T> make_lev(char* ws, const LevelDesc& d) {
   L.colinv = gcp<T>(ws, d.colinv); L.modeinv = gcp<T>(ws, d.modeinv);
   L.x = gmp<T>(ws, d.x); L.f = gmp<T>(ws, d.f); L.r = gmp<T>(ws, d.r);
   L.t1 = gmp<T>(ws, d.t1); L.t2 = gmp<T>(ws, d.t2); L.t3 = gmp<T>(ws, d.t3);
+  L.u = gmp<T>(ws, d.u);
   L.spec = gmp<cpx<T>>(ws, d.spec);
   return L;
 }
@@ -354,13 +355,21 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
                          gptr<const double>(nullptr), gptr<double>(nullptr), 0.0);
     return;
   }
-  if (mode == MODE_VCYCLE) {
+  if (mode == MODE_VCYCLE || mode == MODE_FMG) {
     for (int e = tid(); e < n; e += nthr()) L0.f[e] = (TV)b[e];
     __syncthreads();
-    vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
+    if constexpr (!TR) {
+      if (mode == MODE_FMG) fmg<TV, NZ>(cv, levs, 0, o);
+      else vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
+    } else {
+      vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
+    }
     for (int e = tid(); e < n; e += nthr()) x[e] = (double)L0.x[e];
     return;
   }
+  // full multigrid preconditions forward solves only (it overwrites the level's right-hand side,
+  // so it always runs on the level buffers)
+  const bool use_fmg = !TR && o.cycle == 1;
 
   // ---- FGMRES
   double* V = mp<double>(ws, td.V);
@@ -402,14 +411,19 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
       double* zj = Z + (int64_t)j * n;
       double* w = V + (int64_t)(j + 1) * n;
       // z_j = M^-1 v_j
-      if constexpr (std::is_same<TV, double>::value) {
+      if (std::is_same<TV, double>::value && !use_fmg) {
         const LevSet<TV> lz{ws, &td, as_global(reinterpret_cast<TV*>(vj)),
                             as_global(reinterpret_cast<TV*>(zj))};
         vcycle<TV, NZ, LevSet<TV>, TR>(cv, lz, 0, o);
       } else {
         for (int e = tid(); e < n; e += nthr()) L0.f[e] = (TV)vj[e];
         __syncthreads();
-        vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
+        if constexpr (!TR) {
+          if (use_fmg) fmg<TV, NZ>(cv, levs, 0, o);
+          else vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
+        } else {
+          vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
+        }
         for (int e = tid(); e < n; e += nthr()) zj[e] = (double)L0.x[e];
         __syncthreads();
       }

@@ -26,6 +26,7 @@ struct LevelDesc {
   int64_t colinv;                   // inverse column blocks [nz][nz][nx] (V-cycle precision)
   int64_t modeinv;                  // inverse flat-mode blocks [nz][nz][nx/2+1]
   int64_t x, f, r, t1, t2, t3;      // level vectors [nz][nx] (V-cycle precision)
+  int64_t u;                        // full-multigrid iterate of the level [nz][nx]
   int64_t spec;                     // packed row spectra [(nz+1)/2][nx] complex (V precision)
 };
 
@@ -58,7 +59,8 @@ struct BlockJob {
 struct KOpts {
   int32_t nu1, nu2, coarse_pairs, restart;
   double omega_c, omega_m;
-  int32_t adapt, pad;               // adapt: scale omega_m by the tank's factor (scal + 24)
+  int32_t adapt;                    // scale omega_m by the tank's factor (scal + 24)
+  int32_t cycle;                    // preconditioner: 0 V-cycle, 1 full multigrid
 };
 
 }  // namespace pmgw

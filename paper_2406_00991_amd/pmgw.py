@@ -33,7 +33,8 @@ class Opts(ctypes.Structure):
                 ("rho", ctypes.c_double), ("g", ctypes.c_double), ("nu_visc", ctypes.c_double),
                 ("filt_alpha", ctypes.c_double), ("filt_s", ctypes.c_double),
                 ("filt_fx", ctypes.c_double), ("filt_fz", ctypes.c_double),
-                ("threads", ctypes.c_int32), ("adapt_omega_m", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("adapt_omega_m", ctypes.c_int32),
+                ("cycle", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -66,6 +67,7 @@ def lib():
         L.pmgw_set_geometry.argtypes = [_vp, _vp, _vp, _vp]
         L.laplacian_apply.argtypes = [_vp, _vp, _vp]
         L.pmg_vcycle.argtypes = [_vp, _vp, _vp]
+        L.pmgw_fmg.argtypes = [_vp, _vp, _vp]
         L.poisson_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                     ctypes.POINTER(Info), _vp]
         L.rk4_stage.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp,
@@ -230,6 +232,12 @@ def pmg_vcycle(plan, r, z):
     import torch
     _check(lib().pmg_vcycle(plan._h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
     _trace("pmg_vcycle")
+
+
+def fmg(plan, r, z):
+    import torch
+    _check(lib().pmgw_fmg(plan._h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
+    _trace("pmgw_fmg")
 
 
 def poisson_solve(plan, b, p, rtol=1e-10, maxit=100, sync=True, info_dev=None):

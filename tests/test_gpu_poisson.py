@@ -231,3 +231,39 @@ def test_bar_1024x33_solve(seed):
     ref, inf = krylov.fgmres(lambda v: op.apply(v, go, gn), pr["b"], H, rtol=5e-12, maxit=300)
     assert inf["relres"] <= 2e-11
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", sorted(CASES_VC))
+def test_fmg_parity(case, precision):
+    """pmgw_fmg (paper Alg. 2) against the oracle's full-multigrid cycle, same bars as the
+    V-cycle."""
+    from paper_2406_00991_amd import pmgw
+    probs = CASES_VC[case]()
+    plan = make_plan(probs, precision)
+    z = plan.field()
+    pmgw.fmg(plan, upload2d(probs, "b"), z)
+    tol = 1e-9 if precision == "fp64" else 2e-3
+    for pr, got in zip(probs, download(plan, z)):
+        go, gn = geoms(pr)
+        H = pmg.Hierarchy(pr["nx"], pr["nz"] - 1, go, gn, pmg.PmgOptions(cycle="FMG"))
+        ref = H.fmg(pr["b"])
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"{case} {precision} {pr['nx']}x{pr['nz']}: fmg rel err {err:.2e}", flush=True)
+        assert err <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["stokes_256x17", "batch"])
+def test_solve_with_fmg_preconditioner(case, precision):
+    """FGMRES preconditioned by full multigrid (cycle = FMG) to 1e-10: residual under the oracle's
+    operator <= 1.5e-10 and delta to the oracle's solution <= 1e-8."""
+    probs = CASES_SOLVE[case]()
+    plan = make_plan(probs, precision, cycle=1)
+    p, info = plan.solve(upload2d(probs, "b"), rtol=1e-10, maxit=200)
+    for pr, g, inf in zip(probs, download(plan, p), info):
+        go, gn = geoms(pr)
+        assert inf[1] == 0
+        assert op.relres(g, pr["b"], go, gn) <= 1.5e-10
+        ref = oracle_solution(pr, rtol=1e-12)
+        assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= 1e-8

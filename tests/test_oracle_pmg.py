@@ -141,3 +141,31 @@ def test_mode_damping_rule():
         assert info["converged"]
         its.append(info["iters"])
     assert its[1] < its[0]
+
+
+def test_fmg_linear_and_fewer_iterations():
+    """Alg. 2 as a preconditioner: a fixed linear map, equal on one level to the V-cycle, equal
+    to its correction form (on each level u + V_0(f - A u) with V_0 the cycle from zero, which is
+    how the GPU evaluates it), and FGMRES preconditioned by it converges to the dense solution."""
+    pr = wl.manufactured_sloped(32, 17)
+    g = op.Geometry(pr["h"], pr["eta_old"], pr["L"])
+    H = pmg.Hierarchy(32, 16, g, g, pmg.PmgOptions(cycle="FMG"))
+    rng = np.random.default_rng(5)
+    a, b = rng.standard_normal((2, 17, 32))
+    assert np.abs(H(a + 2 * b) - H(a) - 2 * H(b)).max() <= 1e-10 * np.abs(H(a)).max()
+    H1 = pmg.Hierarchy(32, 2, g, g, pmg.PmgOptions(cycle="FMG"))
+    H1v = pmg.Hierarchy(32, 2, g, g, pmg.PmgOptions())
+    f3 = rng.standard_normal((3, 32))
+    assert np.array_equal(H1(f3), H1v(f3))
+    fs = [a]
+    for l in range(len(H.levels) - 1):
+        fs.append(H.R[l] @ fs[-1])
+    u = H.vcycle(fs[-1], len(H.levels) - 1)
+    for l in range(len(H.levels) - 2, -1, -1):
+        u = H.P[l] @ u
+        u = u + H.vcycle(fs[l] - H.levels[l].apply(u), l)
+    assert np.abs(u - H(a)).max() <= 1e-11 * np.abs(u).max()
+    ref = op.solve_dense(pr["b"], g, g)
+    x, info = krylov.fgmres(lambda v: op.apply(v, g, g), pr["b"], H, rtol=1e-12, maxit=60)
+    assert info["converged"]
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
