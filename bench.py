@@ -50,7 +50,7 @@ def apply_flops(nx, nz):
     return nx * nz * (6 * nz + 10 * math.log2(nx) + 24)
 
 
-def vcycle_flops(nx, nz, nu1=1, nu2=1, coarse_pairs=2):
+def vcycle_flops(nx, nz, nu1=1, nu2=1, coarse_pairs=1):
     tot = 0.0
     rows = level_rows(nz)
     for li, r in enumerate(rows):

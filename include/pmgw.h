@@ -55,7 +55,7 @@ enum { PMGW_CYCLE_V = 0, PMGW_CYCLE_FMG = 1 };
 typedef struct {
     int32_t nu1;            /* pre-smoothing pairs per level [1]                              */
     int32_t nu2;            /* post-smoothing pairs per level [1]                             */
-    int32_t coarse_pairs;   /* smoothing pairs on the coarsest level (order 2) [2]            */
+    int32_t coarse_pairs;   /* smoothing pairs on the coarsest level (order 2) [1]            */
     int32_t restart;        /* FGMRES restart length, 1..32 [30]                              */
     double omega_c;         /* damping of the column-block step [1.0]                         */
     double omega_m;         /* damping of the flat-mode step [1.0]                            */

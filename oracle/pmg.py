@@ -39,7 +39,7 @@ class PmgOptions:
     nu2: int = 1
     omega_c: float = 1.0
     omega_m: float = 1.0
-    coarse_pairs: int = 2
+    coarse_pairs: int = 1
     coarse: str = "smooth"        # "smooth" (fixed pairs) or "exact" (dense LU)
     adapt_omega_m: bool = True    # scale omega_m by mode_damping(geometry)
     cycle: str = "V"              # preconditioner: "V" (Alg. 1) or "FMG" (Alg. 2)

@@ -356,7 +356,7 @@ void pmgw_default_opts(pmgw_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->nu1 = 1;
   o->nu2 = 1;
-  o->coarse_pairs = 2;
+  o->coarse_pairs = 1;
   o->restart = 30;
   o->omega_c = 1.0;
   o->omega_m = 1.0;

@@ -24,6 +24,14 @@ using gptr = PMGW_GLOBAL T*;
 template <typename T>
 __device__ __forceinline__ gptr<T> as_global(T* p) { return (gptr<T>)p; }
 
+// LDS pointers, for code that is not inlined into the function owning the LDS buffer: accesses
+// through them compile to ds_* instructions (a generic pointer would give flat instructions).
+#define PMGW_LOCAL __attribute__((address_space(3)))
+template <typename T>
+using lptr = PMGW_LOCAL T*;
+template <typename T>
+__device__ __forceinline__ lptr<T> as_lds(T* p) { return (lptr<T>)p; }
+
 template <typename T>
 struct cpx {
   T re, im;
@@ -51,6 +59,21 @@ template <typename T>
 __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T>
 __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+
+// Complex values in LDS through lptr, member by member.
+template <typename T>
+__device__ __forceinline__ cpx<T> lld(lptr<const cpx<T>> p, int i) {
+  return {p[i].re, p[i].im};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> lld(lptr<cpx<T>> p, int i) {
+  return {p[i].re, p[i].im};
+}
+template <typename T>
+__device__ __forceinline__ void lst(lptr<cpx<T>> p, int i, cpx<T> v) {
+  p[i].re = v.re;
+  p[i].im = v.im;
+}
 
 __device__ __forceinline__ int tid() { return (int)threadIdx.x; }
 __device__ __forceinline__ int nthr() { return (int)blockDim.x; }
@@ -205,7 +228,7 @@ __device__ __forceinline__ void wave_sync() {
 // of all rows before one wavefront sync and writes all outputs before the next, so the rows' LDS
 // and arithmetic latencies overlap; the twiddles of a butterfly are read once for all rows.
 template <typename T, bool INV, int RM>
-__device__ void fft_wave_m(cpx<T>* a, int nr, int N, int log2N, const cpx<T>* __restrict__ tw,
+__device__ void fft_wave_m(lptr<cpx<T>> a, int nr, int N, int log2N, lptr<const cpx<T>> tw,
                            int lane) {
   int p = 1;
   if (log2N & 1) {
@@ -214,11 +237,11 @@ __device__ void fft_wave_m(cpx<T>* a, int nr, int N, int log2N, const cpx<T>* __
 #pragma unroll
     for (int q = 0; q < RM; ++q) {
       if (q < nr) {
-        const cpx<T>* s = a + q * N;
+        const lptr<cpx<T>> s = a + q * N;
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
           const int i = lane + 64 * it;
-          if (i < h) { r[q][2 * it] = s[i]; r[q][2 * it + 1] = s[i + h]; }
+          if (i < h) { r[q][2 * it] = lld<T>(s, i); r[q][2 * it + 1] = lld<T>(s, i + h); }
         }
       }
     }
@@ -226,13 +249,13 @@ __device__ void fft_wave_m(cpx<T>* a, int nr, int N, int log2N, const cpx<T>* __
 #pragma unroll
     for (int q = 0; q < RM; ++q) {
       if (q < nr) {
-        cpx<T>* d = a + q * N;
+        const lptr<cpx<T>> d = a + q * N;
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
           const int i = lane + 64 * it;
           if (i < h) {
-            d[2 * i] = cadd(r[q][2 * it], r[q][2 * it + 1]);
-            d[2 * i + 1] = csub(r[q][2 * it], r[q][2 * it + 1]);
+            lst<T>(d, 2 * i, cadd(r[q][2 * it], r[q][2 * it + 1]));
+            lst<T>(d, 2 * i + 1, csub(r[q][2 * it], r[q][2 * it + 1]));
           }
         }
       }
@@ -247,13 +270,13 @@ __device__ void fft_wave_m(cpx<T>* a, int nr, int N, int log2N, const cpx<T>* __
 #pragma unroll
     for (int q = 0; q < RM; ++q) {
       if (q < nr) {
-        const cpx<T>* s = a + q * N;
+        const lptr<cpx<T>> s = a + q * N;
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
           const int i = lane + 64 * it;
           if (i < qn) {
-            r[q][4 * it] = s[i]; r[q][4 * it + 1] = s[i + qn];
-            r[q][4 * it + 2] = s[i + 2 * qn]; r[q][4 * it + 3] = s[i + 3 * qn];
+            r[q][4 * it] = lld<T>(s, i); r[q][4 * it + 1] = lld<T>(s, i + qn);
+            r[q][4 * it + 2] = lld<T>(s, i + 2 * qn); r[q][4 * it + 3] = lld<T>(s, i + 3 * qn);
           }
         }
       }
@@ -267,7 +290,7 @@ __device__ void fft_wave_m(cpx<T>* a, int nr, int N, int log2N, const cpx<T>* __
         cpx<T> w1 = {T(1), T(0)}, w2 = w1, w3 = w1;
         if (p > 1) {
           const int t = k * tstep;
-          w1 = tw[t]; w2 = tw[2 * t]; w3 = tw[3 * t];
+          w1 = lld<T>(tw, t); w2 = lld<T>(tw, 2 * t); w3 = lld<T>(tw, 3 * t);
           if (INV) { w1.im = -w1.im; w2.im = -w2.im; w3.im = -w3.im; }
         }
         const int j = ((i - k) << 2) + k;
@@ -284,11 +307,11 @@ __device__ void fft_wave_m(cpx<T>* a, int nr, int N, int log2N, const cpx<T>* __
             const cpx<T> v0 = cadd(u0, u2), v1 = csub(u0, u2), v2 = cadd(u1, u3);
             const cpx<T> dd = csub(u1, u3);
             const cpx<T> v3 = INV ? cpx<T>{-dd.im, dd.re} : cpx<T>{dd.im, -dd.re};
-            cpx<T>* d = a + q * N;
-            d[j] = cadd(v0, v2);
-            d[j + p] = cadd(v1, v3);
-            d[j + 2 * p] = csub(v0, v2);
-            d[j + 3 * p] = csub(v1, v3);
+            const lptr<cpx<T>> d = a + q * N;
+            lst<T>(d, j, cadd(v0, v2));
+            lst<T>(d, j + p, cadd(v1, v3));
+            lst<T>(d, j + 2 * p, csub(v0, v2));
+            lst<T>(d, j + 3 * p, csub(v1, v3));
           }
         }
       }
@@ -395,11 +418,11 @@ __device__ void spectral_rows(int nrows, int N, int log2N, int fftb, LD ld, SM s
       const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
       wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
       wave_sync();
-      fft_wave_m<T, false, kWaveRows>(A, nr, N, log2N, tw, lane);
+      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
       for (int q = 0; q < nr; ++q)
         for (int n = lane; n < N; n += 64) A[q * N + n] = sm(n, A[q * N + n]);
       wave_sync();
-      fft_wave_m<T, true, kWaveRows>(A, nr, N, log2N, tw, lane);
+      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
       wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
       wave_sync();
     }
@@ -462,7 +485,7 @@ __device__ void rows_fft_to_global(int nrows, int N, int log2N, int fftb, LD ld,
       const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
       wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
       wave_sync();
-      fft_wave_m<T, false, kWaveRows>(A, nr, N, log2N, tw, lane);
+      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
       for (int q = 0; q < nr; ++q)
         for (int n = lane; n < N; n += 64) gst<T>(spec, (pp0 + q * nw) * N + n, A[q * N + n]);
       wave_sync();
@@ -526,7 +549,7 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
         }
       }
       wave_sync();
-      fft_wave_m<T, true, kWaveRows>(A, nr, N, log2N, tw, lane);
+      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
       wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
       wave_sync();
     }
@@ -655,6 +678,22 @@ __device__ void col_dsig(int nx, gptr<const T> __restrict__ Ds, gptr<const T> in
   }
 }
 
+// out = D_sigma in for column i only (the calling thread's own column).
+template <typename T, int NZ>
+__device__ __forceinline__ void col_dsig_one(int nx, gptr<const T> __restrict__ Ds,
+                                             gptr<const T> in, gptr<T> out, int i) {
+  T v[NZ];
+#pragma unroll
+  for (int l = 0; l < NZ; ++l) v[l] = in[l * nx + i];
+#pragma unroll 1
+  for (int j = 0; j < NZ; ++j) {
+    T s = T(0);
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) s += Ds[j * NZ + l] * v[l];
+    out[j * nx + i] = s;
+  }
+}
+
 // FIN_FULL: the interior formula on every row (no boundary rows): Div Grad of a field, used for
 // the viscous term of the momentum equations.
 enum : int { FIN_APPLY = 0, FIN_RESID = 1, FIN_COLSTEP = 2, FIN_FULL = 3 };
@@ -666,14 +705,16 @@ enum : int { FIN_APPLY = 0, FIN_RESID = 1, FIN_COLSTEP = 2, FIN_FULL = 3 };
 //   D_x G_x + D_s (a_n G_x + G_z / d_n) + b_n sigma D_s G_x,
 // both contractions taken in one pass over each row of D_s. FIN_APPLY writes A in to out;
 // FIN_RESID writes f - A in; FIN_COLSTEP also applies x += omega B_i^-1 (f - A in)_i column by
-// column (x may alias in).
+// column (x may alias in) and, when t1w is non-null, stores D_s of the updated column there
+// (the next operator application on x then skips its D_s phase).
 template <typename T, int NZ>
 __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __restrict__ Ds,
                                            gptr<const T> __restrict__ sig, const Geo<T>& g,
                                            gptr<const T> in, gptr<const T> ps,
                                            gptr<const T> px, gptr<const T> dxgx, gptr<T> out,
                                            gptr<const T> f, gptr<T> x,
-                                           gptr<const T> __restrict__ cinv, T omega) {
+                                           gptr<const T> __restrict__ cinv, T omega,
+                                           gptr<T> t1w = gptr<T>(nullptr)) {
   for (int i = tid(); i < nx; i += nthr()) {
     const T ao = g.ao[i], bo = g.bo[i], ido = g.ido[i];
     const T an = g.an[i], bn = g.bn[i], idn = g.idn[i], hx = g.hx[i];
@@ -724,14 +765,17 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __res
         for (int l = 0; l < NZ; ++l) s += cinv[(j * NZ + l) * nx + i] * r[l];
         x[j * nx + i] += omega * s;
       }
+      if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
     }
   }
 }
 
-// x = omega B_i^-1 f_i (column step from a zero iterate: the residual is f); TR: B_i^-T.
+// x = omega B_i^-1 f_i (column step from a zero iterate: the residual is f); TR: B_i^-T. When
+// t1w is non-null, also t1w = D_s x for the column.
 template <typename T, int NZ, bool TR = false>
 __device__ void col_solve_zero(int nx, gptr<const T> __restrict__ cinv, gptr<const T> f,
-                               gptr<T> x, T omega) {
+                               gptr<T> x, T omega, gptr<const T> Ds = gptr<const T>(nullptr),
+                               gptr<T> t1w = gptr<T>(nullptr)) {
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZ];
 #pragma unroll
@@ -743,6 +787,7 @@ __device__ void col_solve_zero(int nx, gptr<const T> __restrict__ cinv, gptr<con
       for (int l = 0; l < NZ; ++l) s += cinv[(TR ? l * NZ + j : j * NZ + l) * nx + i] * v[l];
       x[j * nx + i] = omega * s;
     }
+    if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
   }
 }
 
@@ -790,18 +835,21 @@ __device__ void col_prolong_add(int nx, gptr<const T> __restrict__ P, gptr<const
 //   B: t2 = P_x = D_x in                                   (row FFTs)
 //   C: t3 = D_x G_x with G_x = P_x + sx_old P_s            (row FFTs, G_x formed on load)
 //   D: finish (column phase, see col_finish; mode FIN_APPLY, FIN_RESID or FIN_COLSTEP)
+// Phases A and B are independent (both only read `in`), so no barrier separates them; C reads
+// t1 after B's closing barrier. t1_ready: t1 already holds D_s in (phase A is skipped).
+// keep_t1: in FIN_COLSTEP, leave D_s of the updated x in t1.
 template <typename T, int NZ>
 __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int mode,
                                          gptr<const T> in, gptr<T> out, gptr<const T> f,
-                                         gptr<T> x, T omega) {
+                                         gptr<T> x, T omega, bool t1_ready = false,
+                                         bool keep_t1 = false) {
   const int nx = c.nx;
   const gptr<T> t1 = L.t1;
   const gptr<T> t2 = L.t2;
   const gptr<T> t3 = L.t3;
   const gptr<const T> sig = L.sig;
   const Geo<T> g = c.g;
-  col_dsig<T, NZ>(nx, L.Ds, in, t1);
-  __syncthreads();
+  if (!t1_ready) col_dsig<T, NZ>(nx, L.Ds, in, t1);
   dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
              [=](int j, int i) { return in[j * nx + i]; },
              [=](int j, int i, T v) { t2[j * nx + i] = v; });
@@ -810,7 +858,8 @@ __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int m
                return t2[j * nx + i] + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i];
              },
              [=](int j, int i, T v) { t3[j * nx + i] = v; });
-  col_finish<T, NZ>(mode, nx, L.Ds, sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega);
+  col_finish<T, NZ>(mode, nx, L.Ds, sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega,
+                    keep_t1 ? t1 : gptr<T>(nullptr));
   __syncthreads();
 }
 
@@ -906,7 +955,7 @@ __device__ __forceinline__ void op_apply_T(const Ctx<T>& c, const Lev<T>& L, int
   const gptr<T> t3 = L.t3;
   const Geo<T> g = c.g;
   colT_start<T, NZ>(nx, L.Ds, L.sig, g, in, t1, t2);
-  __syncthreads();
+  // no barrier: the next phase reads only `in`; t1 and t2 are read after its closing barrier
   dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
              [=](int j, int i) { return (j == 0 || j == NZ - 1) ? T(0) : in[j * nx + i]; },
              [=](int j, int i, T v) { t3[j * nx + i] = v; });
@@ -921,9 +970,10 @@ __device__ __forceinline__ void op_apply_T(const Ctx<T>& c, const Lev<T>& L, int
 template <typename T, int NZ, bool TR>
 __device__ __forceinline__ void op_any(const Ctx<T>& c, const Lev<T>& L, int mode,
                                        gptr<const T> in, gptr<T> out, gptr<const T> f,
-                                       gptr<T> x, T omega) {
+                                       gptr<T> x, T omega, bool t1_ready = false,
+                                       bool keep_t1 = false) {
   if constexpr (TR) op_apply_T<T, NZ>(c, L, mode, in, out, f, x, omega);
-  else op_apply<T, NZ>(c, L, mode, in, out, f, x, omega);
+  else op_apply<T, NZ>(c, L, mode, in, out, f, x, omega, t1_ready, keep_t1);
 }
 
 template <typename P>
@@ -965,16 +1015,20 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   const int npost = (NZ == 3) ? 0 : (TR ? o.nu1 : o.nu2);
   const int nops = 2 * npre + ((NZ == 3) ? 0 : 1) + 2 * npost;
   bool xzero = true;
+  bool t1x = false;   // forward cycle: t1 holds D_s x (set by column steps)
   for (int q = 0; q < nops; ++q) {
     int kind;
     if (q < 2 * npre) kind = (q & 1) ? second : first;
     else if (NZ != 3 && q == 2 * npre) kind = DOWN;
     else kind = ((q - 2 * npre - 1) & 1) ? second : first;
     if (!xzero)
-      op_any<T, NZ, TR>(c, L, kind == COL ? FIN_COLSTEP : FIN_RESID, L.x, L.r, L.f, L.x, wc);
+      op_any<T, NZ, TR>(c, L, kind == COL ? FIN_COLSTEP : FIN_RESID, L.x, L.r, L.f, L.x, wc,
+                        !TR && t1x, !TR && kind == COL);
+    t1x = !TR && kind == COL;
     if (kind == COL) {
       if (xzero) {
-        col_solve_zero<T, NZ, TR>(nx, L.colinv, L.f, L.x, wc);
+        col_solve_zero<T, NZ, TR>(nx, L.colinv, L.f, L.x, wc, L.Ds,
+                                  TR ? gptr<T>(nullptr) : L.t1);
         __syncthreads();
         xzero = false;
       }
