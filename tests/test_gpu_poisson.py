@@ -267,3 +267,64 @@ def test_solve_with_fmg_preconditioner(case, precision):
         assert op.relres(g, pr["b"], go, gn) <= 1.5e-10
         ref = oracle_solution(pr, rtol=1e-12)
         assert np.linalg.norm(g - ref) / np.linalg.norm(ref) <= 1e-8
+
+
+def test_maximum_size_2048x33():
+    """The largest tank the library accepts (Nx = 2048, Nz = 33, workgroup-wide FFT path):
+    apply parity with the oracle, and a mixed solve whose residual under the oracle's operator
+    meets the tolerance."""
+    x = np.arange(2048) * 2 * math.pi / 2048
+    h = 1.0 + 0.05 * np.cos(x)
+    eta = 0.02 * np.cos(3 * x + 0.4)
+    rng = np.random.default_rng(11)
+    pr = dict(nx=2048, nz=33, L=2 * math.pi, h=h, eta_old=eta, eta_new=eta,
+              b=rng.standard_normal((33, 2048)), rnd=rng.standard_normal((33, 2048)))
+    from paper_2406_00991_amd import pmgw
+    plan = make_plan([pr], "mixed")
+    Ap = plan.apply(upload2d([pr], "rnd"))
+    go, gn = geoms(pr)
+    want = op.apply(pr["rnd"], go, gn)
+    got = download(plan, Ap)[0]
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    p, info = plan.solve(upload2d([pr], "b"), rtol=1e-8, maxit=200)
+    assert info[0][1] == 0, info
+    assert op.relres(download(plan, p)[0], pr["b"], go, gn) <= 1.5e-8
+
+
+@pytest.mark.parametrize("nx", [8, 64])
+def test_single_level_nz3(nx):
+    """Nz = 3 (order 2): the hierarchy has only the coarsest level, so the V-cycle is its smoothing
+    pair; Nx = 8 is the smallest accepted size. Solve parity against the dense oracle."""
+    x = np.arange(nx) * 2 * math.pi / nx
+    h = 1.0 + 0.05 * np.sin(x)
+    eta = 0.03 * np.cos(x)
+    rng = np.random.default_rng(nx)
+    pr = dict(nx=nx, nz=3, L=2 * math.pi, h=h, eta_old=eta, eta_new=0.9 * eta,
+              b=rng.standard_normal((3, nx)))
+    plan = make_plan([pr], "fp64")
+    z = download(plan, plan.vcycle(upload2d([pr], "b")))[0]
+    go, gn = geoms(pr)
+    ref = pmg.Hierarchy(nx, 2, go, gn, pmg.PmgOptions())(pr["b"])
+    assert np.linalg.norm(z - ref) <= 1e-12 * np.linalg.norm(ref)
+    p, info = plan.solve(upload2d([pr], "b"), rtol=1e-12, maxit=200)
+    ref = op.solve_dense(pr["b"], go, gn)
+    assert info[0][1] == 0
+    assert np.linalg.norm(download(plan, p)[0] - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_every_class_in_one_plan():
+    """One tank of every Nz class (3, 5, 9, 17, 33) with ragged Nx in one plan and one call."""
+    shapes = [(8, 3), (16, 5), (32, 9), (64, 17), (2048, 33)]
+    rng = np.random.default_rng(3)
+    probs = []
+    for nx, nz in shapes:
+        x = np.arange(nx) * 2 * math.pi / nx
+        eta = 0.02 * np.cos(x)
+        probs.append(dict(nx=nx, nz=nz, L=2 * math.pi, h=np.ones(nx) + 0.03 * np.sin(x),
+                          eta_old=eta, eta_new=eta, b=rng.standard_normal((nz, nx))))
+    plan = make_plan(probs, "mixed")
+    p, info = plan.solve(upload2d(probs, "b"), rtol=1e-9, maxit=200)
+    for pr, g, inf in zip(probs, download(plan, p), info):
+        go, gn = geoms(pr)
+        assert inf[1] == 0, (pr["nx"], pr["nz"], inf)
+        assert op.relres(g, pr["b"], go, gn) <= 1.5e-9
