@@ -32,6 +32,17 @@ using lptr = PMGW_LOCAL T*;
 template <typename T>
 __device__ __forceinline__ lptr<T> as_lds(T* p) { return (lptr<T>)p; }
 
+// Constant-address-space view of tables that no kernel writes while it runs (the Chebyshev
+// matrices, nodes and transfer matrices of the levels, the sigma filter). Reads at a
+// wavefront-uniform index then compile to scalar loads. Those are waited on through their own
+// counter, so they do not queue behind the vector stores of a column phase, as vector loads of
+// the same tables did (the vector-memory counter retires loads and stores in order).
+#define PMGW_CONST __attribute__((address_space(4)))
+template <typename T>
+using cptr = const PMGW_CONST T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(PMGW_GLOBAL const T* p) { return (cptr<T>)p; }
+
 template <typename T>
 struct cpx {
   T re, im;
@@ -575,6 +586,41 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
   }
 }
 
+// Whether a column phase holds its thread's whole column in registers, with the row loops fully
+// unrolled, so that every vector load of the column is issued before its first store: a load
+// issued after a store also waits for that store, because the vector-memory counter retires both
+// in order, and a row loop that stores row j before loading row j + 1 pays one memory round trip
+// per row. This is done for the float32 levels of up to 17 rows (the mixed-precision V-cycle).
+// Unrolled float64 columns, whose operator the solve kernel inlines at several call sites, and
+// 33-row columns would make the kernels too long for short branches; those keep row loops and
+// read the tables through scalar loads only.
+template <typename T, int NZ>
+constexpr bool kColInRegs = sizeof(T) == 4 && NZ <= 17;
+
+// One output pair p of the flat-mode solve at mode k (rows 2p and 2p + 1, packed as one complex
+// value): ok is stored at k and okc at kc = N - k.
+template <typename T, int NZ, bool TR>
+__device__ __forceinline__ void mode_pair(gptr<const T> __restrict__ minv, int nh, int k, int p,
+                                          const cpx<T> (&rh)[NZ], T scale, cpx<T>& ok,
+                                          cpx<T>& okc) {
+  cpx<T> s0 = {T(0), T(0)}, s1 = {T(0), T(0)};
+  const int j0 = 2 * p, j1 = 2 * p + 1;
+#pragma unroll
+  for (int l = 0; l < NZ; ++l) {
+    const T a = minv[(TR ? l * NZ + j0 : j0 * NZ + l) * nh + k];
+    s0.re += a * rh[l].re;
+    s0.im += a * rh[l].im;
+    if (j1 < NZ) {
+      const T c = minv[(TR ? l * NZ + j1 : j1 * NZ + l) * nh + k];
+      s1.re += c * rh[l].re;
+      s1.im += c * rh[l].im;
+    }
+  }
+  s0.re *= scale; s0.im *= scale; s1.re *= scale; s1.im *= scale;
+  ok = {s0.re - s1.im, s0.im + s1.re};
+  okc = {s0.re + s1.im, s1.re - s0.im};
+}
+
 // Flat-mode line solve in Fourier space: for each mode k in [0, N/2], unpack the spectra of
 // the nz real rows from the packed pairs, multiply by the inverse mode block (real, the same
 // for k and N-k), repack, and fold in the 1/N of the inverse FFT. minv is [NZ][NZ][N/2+1].
@@ -587,6 +633,7 @@ __device__ void mode_matvec(int N, gptr<const T> __restrict__ minv, gptr<cpx<T>>
   const T half = T(0.5), scale = T(1) / T(N);
   for (int k = tid(); k < nh; k += nthr()) {
     const int kc = (N - k) & (N - 1);
+    const bool both = (k != 0 && k != (N >> 1));
     cpx<T> rh[NZ];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -594,24 +641,24 @@ __device__ void mode_matvec(int N, gptr<const T> __restrict__ minv, gptr<cpx<T>>
       rh[2 * p] = {half * (z.re + zc.re), half * (z.im - zc.im)};
       if (2 * p + 1 < NZ) rh[2 * p + 1] = {half * (z.im + zc.im), -half * (z.re - zc.re)};
     }
-#pragma unroll 1
-    for (int p = 0; p < NP; ++p) {
-      cpx<T> s0 = {T(0), T(0)}, s1 = {T(0), T(0)};
-      const int j0 = 2 * p, j1 = 2 * p + 1;
+    if constexpr (kColInRegs<T, NZ>) {
+      // all block reads before the first store (see kColInRegs)
+      cpx<T> ok[NP], okc[NP];
 #pragma unroll
-      for (int l = 0; l < NZ; ++l) {
-        const T a = minv[(TR ? l * NZ + j0 : j0 * NZ + l) * nh + k];
-        s0.re += a * rh[l].re;
-        s0.im += a * rh[l].im;
-        if (j1 < NZ) {
-          const T c = minv[(TR ? l * NZ + j1 : j1 * NZ + l) * nh + k];
-          s1.re += c * rh[l].re;
-          s1.im += c * rh[l].im;
-        }
+      for (int p = 0; p < NP; ++p) mode_pair<T, NZ, TR>(minv, nh, k, p, rh, scale, ok[p], okc[p]);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        gst<T>(spec, p * N + k, ok[p]);
+        if (both) gst<T>(spec, p * N + kc, okc[p]);
       }
-      s0.re *= scale; s0.im *= scale; s1.re *= scale; s1.im *= scale;
-      gst<T>(spec, p * N + k, cpx<T>{s0.re - s1.im, s0.im + s1.re});
-      if (k != 0 && k != (N >> 1)) gst<T>(spec, p * N + kc, cpx<T>{s0.re + s1.im, s1.re - s0.im});
+    } else {
+#pragma unroll 1
+      for (int p = 0; p < NP; ++p) {
+        cpx<T> ok, okc;
+        mode_pair<T, NZ, TR>(minv, nh, k, p, rh, scale, ok, okc);
+        gst<T>(spec, p * N + k, ok);
+        if (both) gst<T>(spec, p * N + kc, okc);
+      }
     }
   }
 }
@@ -663,7 +710,8 @@ __device__ __forceinline__ Lev<T> uni(const Lev<T>& L) {
 
 // out = D_sigma in, column by column.
 template <typename T, int NZ>
-__device__ void col_dsig(int nx, gptr<const T> __restrict__ Ds, gptr<const T> in, gptr<T> out) {
+__device__ void col_dsig(int nx, gptr<const T> Ds_, gptr<const T> in, gptr<T> out) {
+  const cptr<T> Ds = as_const(Ds_);
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZ];
 #pragma unroll
@@ -680,12 +728,25 @@ __device__ void col_dsig(int nx, gptr<const T> __restrict__ Ds, gptr<const T> in
 
 // out = D_sigma in for column i only (the calling thread's own column).
 template <typename T, int NZ>
-__device__ __forceinline__ void col_dsig_one(int nx, gptr<const T> __restrict__ Ds,
-                                             gptr<const T> in, gptr<T> out, int i) {
+__device__ __forceinline__ void col_dsig_one(int nx, cptr<T> Ds, gptr<const T> in, gptr<T> out,
+                                             int i) {
   T v[NZ];
 #pragma unroll
   for (int l = 0; l < NZ; ++l) v[l] = in[l * nx + i];
 #pragma unroll 1
+  for (int j = 0; j < NZ; ++j) {
+    T s = T(0);
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) s += Ds[j * NZ + l] * v[l];
+    out[j * nx + i] = s;
+  }
+}
+
+// out = D_sigma v for column i, from the column's values v in registers.
+template <typename T, int NZ>
+__device__ __forceinline__ void col_dsig_regs(int nx, cptr<T> Ds, const T (&v)[NZ], gptr<T> out,
+                                              int i) {
+#pragma unroll
   for (int j = 0; j < NZ; ++j) {
     T s = T(0);
 #pragma unroll
@@ -708,13 +769,17 @@ enum : int { FIN_APPLY = 0, FIN_RESID = 1, FIN_COLSTEP = 2, FIN_FULL = 3 };
 // column (x may alias in) and, when t1w is non-null, stores D_s of the updated column there
 // (the next operator application on x then skips its D_s phase).
 template <typename T, int NZ>
-__device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __restrict__ Ds,
-                                           gptr<const T> __restrict__ sig, const Geo<T>& g,
+__device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> Ds_,
+                                           gptr<const T> sig_, const Geo<T>& g,
                                            gptr<const T> in, gptr<const T> ps,
                                            gptr<const T> px, gptr<const T> dxgx, gptr<T> out,
                                            gptr<const T> f, gptr<T> x,
                                            gptr<const T> __restrict__ cinv, T omega,
                                            gptr<T> t1w = gptr<T>(nullptr)) {
+  const cptr<T> Ds = as_const(Ds_);
+  const cptr<T> sig = as_const(sig_);
+  const bool full = (mode == FIN_FULL);
+  const bool apply = (mode == FIN_APPLY) || full;   // rows hold A in; otherwise f - A in
   for (int i = tid(); i < nx; i += nthr()) {
     const T ao = g.ao[i], bo = g.bo[i], ido = g.ido[i];
     const T an = g.an[i], bn = g.bn[i], idn = g.idn[i], hx = g.hx[i];
@@ -728,21 +793,8 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __res
       u[l] = an * gx[l] + idn * gz;
       if (l == NZ - 1) gzM = gz;
     }
-    const bool full = (mode == FIN_FULL);
-    if (!full) {
-      const T bed = -(hx * gx[NZ - 1] + gzM);
-      const T top = in[i];
-      if (mode == FIN_APPLY) {
-        out[i] = top;
-        out[(NZ - 1) * nx + i] = bed;
-      } else {
-        out[i] = f[i] - top;
-        out[(NZ - 1) * nx + i] = f[(NZ - 1) * nx + i] - bed;
-      }
-    }
-    const int j0 = full ? 0 : 1, j1 = full ? NZ : NZ - 1;
-#pragma unroll 1
-    for (int j = j0; j < j1; ++j) {
+    // interior row j of A in, given D_x G_x at that row
+    auto row = [&](int j, T dg) {
       T s1 = T(0), s2 = T(0);
 #pragma unroll
       for (int l = 0; l < NZ; ++l) {
@@ -750,22 +802,79 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __res
         s1 += d * u[l];
         s2 += d * gx[l];
       }
-      const T o = dxgx[j * nx + i] + s1 + bn * sig[j] * s2;
-      if (mode == FIN_APPLY || full) out[j * nx + i] = o;
-      else out[j * nx + i] = f[j * nx + i] - o;
-    }
-    if (mode == FIN_COLSTEP) {
-      T r[NZ];
+      return dg + s1 + bn * sig[j] * s2;
+    };
+    if constexpr (kColInRegs<T, NZ>) {
+      T dg[NZ], fv[NZ], xv[NZ], res[NZ];
+      const T top = full ? T(0) : in[i];
 #pragma unroll
-      for (int l = 0; l < NZ; ++l) r[l] = out[l * nx + i];
-#pragma unroll 1
-      for (int j = 0; j < NZ; ++j) {
-        T s = T(0);
+      for (int l = 0; l < NZ; ++l) dg[l] = dxgx[l * nx + i];
+      if (!apply) {
 #pragma unroll
-        for (int l = 0; l < NZ; ++l) s += cinv[(j * NZ + l) * nx + i] * r[l];
-        x[j * nx + i] += omega * s;
+        for (int l = 0; l < NZ; ++l) fv[l] = f[l * nx + i];
       }
-      if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
+      if (mode == FIN_COLSTEP) {
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) xv[l] = x[l * nx + i];
+      }
+      if (!full) {
+        const T bed = -(hx * gx[NZ - 1] + gzM);
+        res[0] = apply ? top : fv[0] - top;
+        res[NZ - 1] = apply ? bed : fv[NZ - 1] - bed;
+      }
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) {
+        if (!full && (j == 0 || j == NZ - 1)) continue;
+        const T o = row(j, dg[j]);
+        res[j] = apply ? o : fv[j] - o;
+      }
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) out[l * nx + i] = res[l];
+      if (mode == FIN_COLSTEP) {
+        T xn[NZ];
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) {
+          T s = T(0);
+#pragma unroll
+          for (int l = 0; l < NZ; ++l) s += cinv[(j * NZ + l) * nx + i] * res[l];
+          xn[j] = xv[j] + omega * s;
+        }
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) x[l * nx + i] = xn[l];
+        if (t1w) col_dsig_regs<T, NZ>(nx, Ds, xn, t1w, i);
+      }
+    } else {
+      if (!full) {
+        const T bed = -(hx * gx[NZ - 1] + gzM);
+        const T top = in[i];
+        if (mode == FIN_APPLY) {
+          out[i] = top;
+          out[(NZ - 1) * nx + i] = bed;
+        } else {
+          out[i] = f[i] - top;
+          out[(NZ - 1) * nx + i] = f[(NZ - 1) * nx + i] - bed;
+        }
+      }
+      const int j0 = full ? 0 : 1, j1 = full ? NZ : NZ - 1;
+#pragma unroll 1
+      for (int j = j0; j < j1; ++j) {
+        const T o = row(j, dxgx[j * nx + i]);
+        if (apply) out[j * nx + i] = o;
+        else out[j * nx + i] = f[j * nx + i] - o;
+      }
+      if (mode == FIN_COLSTEP) {
+        T r[NZ];
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) r[l] = out[l * nx + i];
+#pragma unroll 1
+        for (int j = 0; j < NZ; ++j) {
+          T s = T(0);
+#pragma unroll
+          for (int l = 0; l < NZ; ++l) s += cinv[(j * NZ + l) * nx + i] * r[l];
+          x[j * nx + i] += omega * s;
+        }
+        if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
+      }
     }
   }
 }
@@ -774,27 +883,43 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> __res
 // t1w is non-null, also t1w = D_s x for the column.
 template <typename T, int NZ, bool TR = false>
 __device__ void col_solve_zero(int nx, gptr<const T> __restrict__ cinv, gptr<const T> f,
-                               gptr<T> x, T omega, gptr<const T> Ds = gptr<const T>(nullptr),
+                               gptr<T> x, T omega, gptr<const T> Ds_ = gptr<const T>(nullptr),
                                gptr<T> t1w = gptr<T>(nullptr)) {
+  const cptr<T> Ds = as_const(Ds_);
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZ];
 #pragma unroll
     for (int l = 0; l < NZ; ++l) v[l] = f[l * nx + i];
-#pragma unroll 1
-    for (int j = 0; j < NZ; ++j) {
-      T s = T(0);
+    if constexpr (kColInRegs<T, NZ>) {
+      T xn[NZ];
 #pragma unroll
-      for (int l = 0; l < NZ; ++l) s += cinv[(TR ? l * NZ + j : j * NZ + l) * nx + i] * v[l];
-      x[j * nx + i] = omega * s;
+      for (int j = 0; j < NZ; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) s += cinv[(TR ? l * NZ + j : j * NZ + l) * nx + i] * v[l];
+        xn[j] = omega * s;
+      }
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) x[l * nx + i] = xn[l];
+      if (t1w) col_dsig_regs<T, NZ>(nx, Ds, xn, t1w, i);
+    } else {
+#pragma unroll 1
+      for (int j = 0; j < NZ; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) s += cinv[(TR ? l * NZ + j : j * NZ + l) * nx + i] * v[l];
+        x[j * nx + i] = omega * s;
+      }
+      if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
     }
-    if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
   }
 }
 
 // fc = R r (restriction to the next coarser order, NZC = (NZ+1)/2 rows).
 template <typename T, int NZ>
-__device__ void col_restrict(int nx, gptr<const T> __restrict__ R, gptr<const T> r, gptr<T> fc) {
+__device__ void col_restrict(int nx, gptr<const T> R_, gptr<const T> r, gptr<T> fc) {
   constexpr int NZC = (NZ + 1) / 2;
+  const cptr<T> R = as_const(R_);
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZ];
 #pragma unroll
@@ -811,19 +936,32 @@ __device__ void col_restrict(int nx, gptr<const T> __restrict__ R, gptr<const T>
 
 // x += P xc (prolongation from the next coarser order).
 template <typename T, int NZ>
-__device__ void col_prolong_add(int nx, gptr<const T> __restrict__ P, gptr<const T> xc,
-                                gptr<T> x) {
+__device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr<T> x) {
   constexpr int NZC = (NZ + 1) / 2;
+  const cptr<T> P = as_const(P_);
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZC];
 #pragma unroll
     for (int c = 0; c < NZC; ++c) v[c] = xc[c * nx + i];
-#pragma unroll 1
-    for (int j = 0; j < NZ; ++j) {
-      T s = T(0);
+    if constexpr (kColInRegs<T, NZ>) {
+      T xv[NZ];
 #pragma unroll
-      for (int c = 0; c < NZC; ++c) s += P[j * NZC + c] * v[c];
-      x[j * nx + i] += s;
+      for (int j = 0; j < NZ; ++j) xv[j] = x[j * nx + i];
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int c = 0; c < NZC; ++c) s += P[j * NZC + c] * v[c];
+        x[j * nx + i] = xv[j] + s;
+      }
+    } else {
+#pragma unroll 1
+      for (int j = 0; j < NZ; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int c = 0; c < NZC; ++c) s += P[j * NZC + c] * v[c];
+        x[j * nx + i] += s;
+      }
     }
   }
 }

@@ -302,6 +302,48 @@ __global__ void __launch_bounds__(64) k_blocks(const TankDesc* __restrict__ desc
 
 // ----------------------------------------------------------------------------- solve kernel
 
+// Elementwise passes of the Krylov loop over the workgroup's share of a field: each thread takes
+// kEw of its elements at a time (e, e + nthr(), ...), issues all their loads, then computes and
+// stores. A load issued after a store waits for that store (the vector-memory counter retires
+// both in order), so one element at a time would cost a memory round trip per element. The
+// order in which a thread visits its elements, and so every per-thread sum, is unchanged.
+constexpr int kEw = 4;
+
+// dst[e] = (TD) src[e]
+template <typename TD, typename TS, typename PD, typename PS>
+__device__ __forceinline__ void ew_copy(int n, PD dst, PS src) {
+  for (int e0 = tid(); e0 < n; e0 += kEw * nthr()) {
+    TS v[kEw];
+#pragma unroll
+    for (int q = 0; q < kEw; ++q) {
+      const int e = e0 + q * nthr();
+      if (e < n) v[q] = src[e];
+    }
+#pragma unroll
+    for (int q = 0; q < kEw; ++q) {
+      const int e = e0 + q * nthr();
+      if (e < n) dst[e] = (TD)v[q];
+    }
+  }
+}
+
+// p[e] *= a
+__device__ __forceinline__ void ew_scale(int n, double* p, double a) {
+  for (int e0 = tid(); e0 < n; e0 += kEw * nthr()) {
+    double v[kEw];
+#pragma unroll
+    for (int q = 0; q < kEw; ++q) {
+      const int e = e0 + q * nthr();
+      if (e < n) v[q] = p[e];
+    }
+#pragma unroll
+    for (int q = 0; q < kEw; ++q) {
+      const int e = e0 + q * nthr();
+      if (e < n) p[e] = v[q] * a;
+    }
+  }
+}
+
 // Givens/Hessenberg state of FGMRES in LDS.
 struct KrylovLds {
   double H[(kMaxRestart + 1) * kMaxRestart];
@@ -356,7 +398,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
     return;
   }
   if (mode == MODE_VCYCLE || mode == MODE_FMG) {
-    for (int e = tid(); e < n; e += nthr()) L0.f[e] = (TV)b[e];
+    ew_copy<TV, double>(n, L0.f, b);
     __syncthreads();
     if constexpr (!TR) {
       if (mode == MODE_FMG) fmg<TV, NZ>(cv, levs, 0, o);
@@ -364,7 +406,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
     } else {
       vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
     }
-    for (int e = tid(); e < n; e += nthr()) x[e] = (double)L0.x[e];
+    ew_copy<double, TV>(n, x, L0.x);
     return;
   }
   // full multigrid preconditions forward solves only (it overwrites the level's right-hand side,
@@ -400,7 +442,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
     if (rel <= rtol) { status = ST_OK; break; }
     if (it >= maxit) { status = ST_NOCONV; break; }
     const double ib = 1.0 / beta;
-    for (int e = tid(); e < n; e += nthr()) V[e] *= ib;
+    ew_scale(n, V, ib);
     if (tid() == 0) K.g[0] = beta;
     __syncthreads();
     const int mm = min(m, maxit - it);
@@ -416,7 +458,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
                             as_global(reinterpret_cast<TV*>(zj))};
         vcycle<TV, NZ, LevSet<TV>, TR>(cv, lz, 0, o);
       } else {
-        for (int e = tid(); e < n; e += nthr()) L0.f[e] = (TV)vj[e];
+        ew_copy<TV, double>(n, L0.f, vj);
         __syncthreads();
         if constexpr (!TR) {
           if (use_fmg) fmg<TV, NZ>(cv, levs, 0, o);
@@ -424,7 +466,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
         } else {
           vcycle<TV, NZ, LevSet<TV>, TR>(cv, levs, 0, o);
         }
-        for (int e = tid(); e < n; e += nthr()) zj[e] = (double)L0.x[e];
+        ew_copy<double, TV>(n, zj, L0.x);
         __syncthreads();
       }
       // w = A z_j
@@ -436,10 +478,25 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
         const double* vprev = (i > 0) ? V + (int64_t)(i - 1) * n : nullptr;
         const double* vi = (i <= j) ? V + (int64_t)i * n : nullptr;
         double acc = 0.0;
-        for (int e = tid(); e < n; e += nthr()) {
-          double we = w[e];
-          if (i > 0) { we -= hprev * vprev[e]; w[e] = we; }
-          acc += (i <= j) ? we * vi[e] : we * we;
+        for (int e0 = tid(); e0 < n; e0 += kEw * nthr()) {
+          double we[kEw], vp[kEw], vv[kEw];
+#pragma unroll
+          for (int q = 0; q < kEw; ++q) {
+            const int e = e0 + q * nthr();
+            if (e < n) {
+              we[q] = w[e];
+              if (i > 0) vp[q] = vprev[e];
+              if (i <= j) vv[q] = vi[e];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < kEw; ++q) {
+            const int e = e0 + q * nthr();
+            if (e < n) {
+              if (i > 0) { we[q] -= hprev * vp[q]; w[e] = we[q]; }
+              acc += (i <= j) ? we[q] * vv[q] : we[q] * we[q];
+            }
+          }
         }
         const double hv = block_sum(acc, K.red);
         if (i <= j) {
@@ -450,7 +507,7 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
           if (tid() == 0) K.H[(j + 1) * kMaxRestart + j] = hn;
           if (hn > 0.0 && isfinite(hn)) {
             const double ih = 1.0 / hn;
-            for (int e = tid(); e < n; e += nthr()) w[e] *= ih;
+            ew_scale(n, w, ih);
           }
         }
       }
@@ -490,10 +547,26 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
       }
     }
     __syncthreads();
-    for (int e = tid(); e < n; e += nthr()) {
-      double acc = x[e];
-      for (int i = 0; i < kdone; ++i) acc += K.y[i] * Z[(int64_t)i * n + e];
-      x[e] = acc;
+    for (int e0 = tid(); e0 < n; e0 += kEw * nthr()) {
+      double acc[kEw];
+#pragma unroll
+      for (int q = 0; q < kEw; ++q) {
+        const int e = e0 + q * nthr();
+        if (e < n) acc[q] = x[e];
+      }
+      for (int i = 0; i < kdone; ++i) {
+        const double yi = K.y[i];
+#pragma unroll
+        for (int q = 0; q < kEw; ++q) {
+          const int e = e0 + q * nthr();
+          if (e < n) acc[q] += yi * Z[(int64_t)i * n + e];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kEw; ++q) {
+        const int e = e0 + q * nthr();
+        if (e < n) x[e] = acc[q];
+      }
     }
     __syncthreads();
   }
