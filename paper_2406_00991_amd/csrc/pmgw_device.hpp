@@ -405,6 +405,70 @@ __device__ __forceinline__ void wave_store_pairs(const cpx<T>* A, int nr, int N,
   }
 }
 
+// Store target of an inverse row FFT: x = w v, or x += w v when add (x has row stride nx).
+template <typename T>
+struct Axpy {
+  gptr<T> x;
+  int nx;
+  T w;
+  bool add;
+  __device__ __forceinline__ void operator()(int j, int i, T v) const {
+    if (add) x[j * nx + i] += w * v;
+    else x[j * nx + i] = w * v;
+  }
+};
+
+// wave_store_pairs for an Axpy target. With add, every old value of x is loaded before the first
+// store: a load issued after a store waits for that store (the vector-memory counter retires both
+// in order), which would cost a memory round trip per element.
+template <typename T>
+__device__ __forceinline__ void wave_axpy_pairs(const cpx<T>* A, int nr, int N, int lane,
+                                                int pp0, int nw, int nrows, const Axpy<T>& st) {
+  cpx<T> v[kWaveRows][8], o[kWaveRows][8];
+#pragma unroll
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) v[q][it] = A[q * N + n];
+      }
+    }
+  }
+  if (st.add) {
+#pragma unroll
+    for (int q = 0; q < kWaveRows; ++q) {
+      if (q < nr) {
+        const int ra = 2 * (pp0 + q * nw);
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int n = lane + 64 * it;
+          if (n < N) {
+            o[q][it].re = st.x[ra * st.nx + n];
+            o[q][it].im = (ra + 1 < nrows) ? st.x[(ra + 1) * st.nx + n] : T(0);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+      const int ra = 2 * (pp0 + q * nw);
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) {
+          st.x[ra * st.nx + n] = st.add ? o[q][it].re + st.w * v[q][it].re : st.w * v[q][it].re;
+          if (ra + 1 < nrows)
+            st.x[(ra + 1) * st.nx + n] =
+                st.add ? o[q][it].im + st.w * v[q][it].im : st.w * v[q][it].im;
+        }
+      }
+    }
+  }
+}
+
 // Whether the per-wavefront FFT path applies: 64 <= N <= 512 and one N-row per wavefront fits.
 template <typename T>
 __device__ __forceinline__ bool fft_by_wave(int N, int fftb) {
@@ -561,7 +625,10 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
       }
       wave_sync();
       fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
-      wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
+      if constexpr (std::is_same<ST, Axpy<T>>::value)
+        wave_axpy_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
+      else
+        wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
       wave_sync();
     }
     __syncthreads();
@@ -592,10 +659,16 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
 // in order, and a row loop that stores row j before loading row j + 1 pays one memory round trip
 // per row. This is done for the float32 levels of up to 17 rows (the mixed-precision V-cycle).
 // Unrolled float64 columns, whose operator the solve kernel inlines at several call sites, and
-// 33-row columns would make the kernels too long for short branches; those keep row loops and
-// read the tables through scalar loads only.
+// 33-row columns would make the kernels too long for short branches; those keep row loops that
+// step through the rows in chunks of kRowChunk.
 template <typename T, int NZ>
 constexpr bool kColInRegs = sizeof(T) == 4 && NZ <= 17;
+
+// Rows per step of the row loops that are not unrolled: the loads of a chunk of rows are issued
+// together before its stores, which cuts the round trips of a column phase by that factor (two
+// for the float64 33-row columns, whose loads in flight would otherwise crowd the registers).
+template <typename T, int NZ>
+constexpr int kRowChunk = (sizeof(T) == 8 && NZ > 17) ? 2 : 4;
 
 // One output pair p of the flat-mode solve at mode k (rows 2p and 2p + 1, packed as one complex
 // value): ok is stored at k and okc at kc = N - k.
@@ -855,23 +928,45 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> Ds_,
           out[(NZ - 1) * nx + i] = f[(NZ - 1) * nx + i] - bed;
         }
       }
+      constexpr int C = kRowChunk<T, NZ>;
       const int j0 = full ? 0 : 1, j1 = full ? NZ : NZ - 1;
 #pragma unroll 1
-      for (int j = j0; j < j1; ++j) {
-        const T o = row(j, dxgx[j * nx + i]);
-        if (apply) out[j * nx + i] = o;
-        else out[j * nx + i] = f[j * nx + i] - o;
+      for (int j = j0; j < j1; j += C) {
+        T dg[C], fv[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+          if (j + q < j1) {
+            dg[q] = dxgx[(j + q) * nx + i];
+            if (!apply) fv[q] = f[(j + q) * nx + i];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+          if (j + q < j1) {
+            const T o = row(j + q, dg[q]);
+            out[(j + q) * nx + i] = apply ? o : fv[q] - o;
+          }
+        }
       }
       if (mode == FIN_COLSTEP) {
         T r[NZ];
 #pragma unroll
         for (int l = 0; l < NZ; ++l) r[l] = out[l * nx + i];
 #pragma unroll 1
-        for (int j = 0; j < NZ; ++j) {
-          T s = T(0);
+        for (int j = 0; j < NZ; j += C) {
+          T s[C], xo[C];
 #pragma unroll
-          for (int l = 0; l < NZ; ++l) s += cinv[(j * NZ + l) * nx + i] * r[l];
-          x[j * nx + i] += omega * s;
+          for (int q = 0; q < C; ++q) {
+            s[q] = T(0);
+            if (j + q < NZ) {
+              xo[q] = x[(j + q) * nx + i];
+#pragma unroll
+              for (int l = 0; l < NZ; ++l) s[q] += cinv[((j + q) * NZ + l) * nx + i] * r[l];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < C; ++q)
+            if (j + q < NZ) x[(j + q) * nx + i] = xo[q] + omega * s[q];
         }
         if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
       }
@@ -903,12 +998,23 @@ __device__ void col_solve_zero(int nx, gptr<const T> __restrict__ cinv, gptr<con
       for (int l = 0; l < NZ; ++l) x[l * nx + i] = xn[l];
       if (t1w) col_dsig_regs<T, NZ>(nx, Ds, xn, t1w, i);
     } else {
+      constexpr int C = kRowChunk<T, NZ>;
 #pragma unroll 1
-      for (int j = 0; j < NZ; ++j) {
-        T s = T(0);
+      for (int j = 0; j < NZ; j += C) {
+        T s[C];
 #pragma unroll
-        for (int l = 0; l < NZ; ++l) s += cinv[(TR ? l * NZ + j : j * NZ + l) * nx + i] * v[l];
-        x[j * nx + i] = omega * s;
+        for (int q = 0; q < C; ++q) {
+          s[q] = T(0);
+          const int jq = j + q;
+          if (jq < NZ) {
+#pragma unroll
+            for (int l = 0; l < NZ; ++l)
+              s[q] += cinv[(TR ? l * NZ + jq : jq * NZ + l) * nx + i] * v[l];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+          if (j + q < NZ) x[(j + q) * nx + i] = omega * s[q];
       }
       if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
     }
@@ -955,12 +1061,22 @@ __device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr
         x[j * nx + i] = xv[j] + s;
       }
     } else {
+      constexpr int C = kRowChunk<T, NZ>;
 #pragma unroll 1
-      for (int j = 0; j < NZ; ++j) {
-        T s = T(0);
+      for (int j = 0; j < NZ; j += C) {
+        T s[C], xo[C];
 #pragma unroll
-        for (int c = 0; c < NZC; ++c) s += P[j * NZC + c] * v[c];
-        x[j * nx + i] += s;
+        for (int q = 0; q < C; ++q) {
+          s[q] = T(0);
+          if (j + q < NZ) {
+            xo[q] = x[(j + q) * nx + i];
+#pragma unroll
+            for (int c = 0; c < NZC; ++c) s[q] += P[(j + q) * NZC + c] * v[c];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+          if (j + q < NZ) x[(j + q) * nx + i] = xo[q] + s[q];
       }
     }
   }
@@ -1176,13 +1292,7 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
                             [=](int j, int i) { return r[j * nx + i]; }, L.spec);
       mode_matvec<T, NZ, TR>(nx, L.modeinv, L.spec);
       __syncthreads();
-      const gptr<T> x = L.x;
-      if (xzero)
-        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.fftb, L.spec,
-                                 [=](int j, int i, T v) { x[j * nx + i] = wm * v; });
-      else
-        rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.fftb, L.spec,
-                                 [=](int j, int i, T v) { x[j * nx + i] += wm * v; });
+      rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.fftb, L.spec, Axpy<T>{L.x, nx, wm, !xzero});
       xzero = false;
     } else {
       if constexpr (NZ > 3) {
