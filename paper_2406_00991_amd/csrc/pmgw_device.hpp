@@ -531,18 +531,111 @@ __device__ void spectral_rows(int nrows, int N, int log2N, int fftb, LD ld, SM s
   }
 }
 
-// D_x of `nrows` real rows: the spectral multiplier i kappa_k / N with the Nyquist entry zeroed.
+// The spectral multiplier of D_x for an unscaled inverse FFT: i kappa_k / N, Nyquist entry zeroed.
+template <typename T>
+struct DxMul {
+  int N;
+  T kfac;
+  __device__ __forceinline__ cpx<T> operator()(int n, cpx<T> v) const {
+    const T scale = T(1) / T(N);
+    const int kk = (n <= (N >> 1)) ? n : n - N;
+    const T kap = (n == (N >> 1)) ? T(0) : kfac * T(kk) * scale;
+    return cpx<T>{-kap * v.im, kap * v.re};
+  }
+};
+
+// D_x of `nrows` real rows.
 template <typename T, class LD, class ST>
 __device__ __forceinline__ void dx_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld,
                                         ST st) {
-  const T scale = T(1) / T(N);
-  spectral_rows<T>(nrows, N, log2N, fftb, ld,
-                   [=](int n, cpx<T> v) {
-                     const int kk = (n <= (N >> 1)) ? n : n - N;
-                     const T kap = (n == (N >> 1)) ? T(0) : kfac * T(kk) * scale;
-                     return cpx<T>{-kap * v.im, kap * v.re};
-                   },
-                   st);
+  spectral_rows<T>(nrows, N, log2N, fftb, ld, DxMul<T>{N, kfac}, st);
+}
+
+// Between the two passes of dx2_rows: the wavefront's rows of p_x = D_x in (packed pairs in LDS)
+// are stored through stx and replaced in LDS by g = mid(j, i, p_x). mid's global reads are issued
+// before the stores (a load issued after a store waits for it).
+template <typename T, class STX, class MID>
+__device__ __forceinline__ void wave_mid_pairs(cpx<T>* A, int nr, int N, int lane, int pp0,
+                                               int nw, int nrows, STX stx, MID mid) {
+  cpx<T> v[kWaveRows][8], gv[kWaveRows][8];
+#pragma unroll
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) v[q][it] = A[q * N + n];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+      const int ra = 2 * (pp0 + q * nw);
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N)
+          gv[q][it] = {mid(ra, n, v[q][it].re),
+                       (ra + 1 < nrows) ? mid(ra + 1, n, v[q][it].im) : T(0)};
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kWaveRows; ++q) {
+    if (q < nr) {
+      const int ra = 2 * (pp0 + q * nw);
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int n = lane + 64 * it;
+        if (n < N) {
+          stx(ra, n, v[q][it].re);
+          if (ra + 1 < nrows) stx(ra + 1, n, v[q][it].im);
+          A[q * N + n] = gv[q][it];
+        }
+      }
+    }
+  }
+}
+
+// Two chained D_x passes over the same rows (phases B and C of the operator): p_x = D_x in is
+// stored through stx, then D_x g with g = mid(j, i, p_x) is stored through sto. On the wavefront
+// path each wavefront keeps its rows in LDS from the first pass to the second, so the second pass
+// needs no workgroup barrier and does not read p_x back; mid may read only fields completed
+// before the call. Otherwise the two passes run one after the other, the second reading p_x back
+// through ldx. Ends with a barrier.
+template <typename T, class LD, class STX, class LDX, class MID, class STO>
+__device__ void dx2_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld, STX stx, LDX ldx,
+                         MID mid, STO sto) {
+  const DxMul<T> sm{N, kfac};
+  if (!fft_by_wave<T>(N, fftb)) {
+    spectral_rows<T>(nrows, N, log2N, fftb, ld, sm, stx);
+    spectral_rows<T>(nrows, N, log2N, fftb, [=](int j, int i) { return mid(j, i, ldx(j, i)); },
+                     sm, sto);
+    return;
+  }
+  const int npairs = (nrows + 1) >> 1;
+  const cpx<T>* tw = lds_tw<T>(fftb, N);
+  const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
+  const int R = wave_rows<T>(N, fftb, npairs);
+  cpx<T>* A = fft_buf<T>() + w * R * N;
+  for (int base = 0; base < npairs; base += nw * R) {
+    const int pp0 = base + w;
+    const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
+    wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
+    for (int pass = 0; pass < 2; ++pass) {
+      wave_sync();
+      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+      for (int q = 0; q < nr; ++q)
+        for (int n = lane; n < N; n += 64) A[q * N + n] = sm(n, A[q * N + n]);
+      wave_sync();
+      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+      if (pass == 0) wave_mid_pairs<T>(A, nr, N, lane, pp0, nw, nrows, stx, mid);
+    }
+    wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, sto);
+    wave_sync();
+  }
+  __syncthreads();
 }
 
 // Forward FFT of real rows, packed in pairs, into spec[(nrows+1)/2][N] (global). Barrier at end.
@@ -1087,10 +1180,10 @@ __device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr
 // The composite operator on one level of NZ rows (paper eq. poissonp, eq. bcpd, eq. bcpdneu):
 //   A: t1 = P_s = D_s in                                   (column phase)
 //   B: t2 = P_x = D_x in                                   (row FFTs)
-//   C: t3 = D_x G_x with G_x = P_x + sx_old P_s            (row FFTs, G_x formed on load)
+//   C: t3 = D_x G_x with G_x = P_x + sx_old P_s            (row FFTs, G_x formed in LDS)
 //   D: finish (column phase, see col_finish; mode FIN_APPLY, FIN_RESID or FIN_COLSTEP)
-// Phases A and B are independent (both only read `in`), so no barrier separates them; C reads
-// t1 after B's closing barrier. t1_ready: t1 already holds D_s in (phase A is skipped).
+// B and C run fused per wavefront (dx2_rows), so C reads P_x from LDS without a barrier; a
+// barrier after A makes t1 complete first. t1_ready: t1 already holds D_s in (A is skipped).
 // keep_t1: in FIN_COLSTEP, leave D_s of the updated x in t1.
 template <typename T, int NZ>
 __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int mode,
@@ -1103,15 +1196,16 @@ __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int m
   const gptr<T> t3 = L.t3;
   const gptr<const T> sig = L.sig;
   const Geo<T> g = c.g;
-  if (!t1_ready) col_dsig<T, NZ>(nx, L.Ds, in, t1);
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
-             [=](int j, int i) { return in[j * nx + i]; },
-             [=](int j, int i, T v) { t2[j * nx + i] = v; });
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
-             [=](int j, int i) {
-               return t2[j * nx + i] + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i];
-             },
-             [=](int j, int i, T v) { t3[j * nx + i] = v; });
+  if (!t1_ready) {
+    col_dsig<T, NZ>(nx, L.Ds, in, t1);
+    __syncthreads();   // phase C reads t1
+  }
+  dx2_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
+              [=](int j, int i) { return in[j * nx + i]; },
+              [=](int j, int i, T v) { t2[j * nx + i] = v; },
+              [=](int j, int i) { return t2[j * nx + i]; },
+              [=](int j, int i, T px) { return px + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i]; },
+              [=](int j, int i, T v) { t3[j * nx + i] = v; });
   col_finish<T, NZ>(mode, nx, L.Ds, sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega,
                     keep_t1 ? t1 : gptr<T>(nullptr));
   __syncthreads();
