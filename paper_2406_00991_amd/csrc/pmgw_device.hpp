@@ -602,40 +602,43 @@ __device__ __forceinline__ void wave_mid_pairs(cpx<T>* A, int nr, int N, int lan
 // stored through stx, then D_x g with g = mid(j, i, p_x) is stored through sto. On the wavefront
 // path each wavefront keeps its rows in LDS from the first pass to the second, so the second pass
 // needs no workgroup barrier and does not read p_x back; mid may read only fields completed
-// before the call. Otherwise the two passes run one after the other, the second reading p_x back
-// through ldx. Ends with a barrier.
+// before the call. Otherwise, and always for float64 rows (whose doubled register footprint in
+// the fused form made the float64 solve slower), the two passes run one after the other, the
+// second reading p_x back through ldx. Ends with a barrier.
 template <typename T, class LD, class STX, class LDX, class MID, class STO>
 __device__ void dx2_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld, STX stx, LDX ldx,
                          MID mid, STO sto) {
   const DxMul<T> sm{N, kfac};
-  if (!fft_by_wave<T>(N, fftb)) {
+  if (sizeof(T) == 8 || !fft_by_wave<T>(N, fftb)) {
     spectral_rows<T>(nrows, N, log2N, fftb, ld, sm, stx);
     spectral_rows<T>(nrows, N, log2N, fftb, [=](int j, int i) { return mid(j, i, ldx(j, i)); },
                      sm, sto);
     return;
   }
-  const int npairs = (nrows + 1) >> 1;
-  const cpx<T>* tw = lds_tw<T>(fftb, N);
-  const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
-  const int R = wave_rows<T>(N, fftb, npairs);
-  cpx<T>* A = fft_buf<T>() + w * R * N;
-  for (int base = 0; base < npairs; base += nw * R) {
-    const int pp0 = base + w;
-    const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
-    wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
-    for (int pass = 0; pass < 2; ++pass) {
+  if constexpr (sizeof(T) == 4) {
+    const int npairs = (nrows + 1) >> 1;
+    const cpx<T>* tw = lds_tw<T>(fftb, N);
+    const int lane = tid() & 63, w = tid() >> 6, nw = nthr() >> 6;
+    const int R = wave_rows<T>(N, fftb, npairs);
+    cpx<T>* A = fft_buf<T>() + w * R * N;
+    for (int base = 0; base < npairs; base += nw * R) {
+      const int pp0 = base + w;
+      const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
+      wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
+      for (int pass = 0; pass < 2; ++pass) {
+        wave_sync();
+        fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+        for (int q = 0; q < nr; ++q)
+          for (int n = lane; n < N; n += 64) A[q * N + n] = sm(n, A[q * N + n]);
+        wave_sync();
+        fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+        if (pass == 0) wave_mid_pairs<T>(A, nr, N, lane, pp0, nw, nrows, stx, mid);
+      }
+      wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, sto);
       wave_sync();
-      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
-      for (int q = 0; q < nr; ++q)
-        for (int n = lane; n < N; n += 64) A[q * N + n] = sm(n, A[q * N + n]);
-      wave_sync();
-      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
-      if (pass == 0) wave_mid_pairs<T>(A, nr, N, lane, pp0, nw, nrows, stx, mid);
     }
-    wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, sto);
-    wave_sync();
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Forward FFT of real rows, packed in pairs, into spec[(nrows+1)/2][N] (global). Barrier at end.
@@ -921,6 +924,20 @@ __device__ __forceinline__ void col_dsig_regs(int nx, cptr<T> Ds, const T (&v)[N
   }
 }
 
+// fc = R v for column i (restriction to NZC = (NZ+1)/2 rows), from the column v in registers.
+template <typename T, int NZ>
+__device__ __forceinline__ void col_restrict_regs(int nx, cptr<T> R, const T (&v)[NZ],
+                                                  gptr<T> fc, int i) {
+  constexpr int NZC = (NZ + 1) / 2;
+#pragma unroll 1
+  for (int j = 0; j < NZC; ++j) {
+    T s = T(0);
+#pragma unroll
+    for (int l = 0; l < NZ; ++l) s += R[j * NZ + l] * v[l];
+    fc[j * nx + i] = s;
+  }
+}
+
 // FIN_FULL: the interior formula on every row (no boundary rows): Div Grad of a field, used for
 // the viscous term of the momentum equations.
 enum : int { FIN_APPLY = 0, FIN_RESID = 1, FIN_COLSTEP = 2, FIN_FULL = 3 };
@@ -941,9 +958,13 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> Ds_,
                                            gptr<const T> px, gptr<const T> dxgx, gptr<T> out,
                                            gptr<const T> f, gptr<T> x,
                                            gptr<const T> __restrict__ cinv, T omega,
-                                           gptr<T> t1w = gptr<T>(nullptr)) {
+                                           gptr<T> t1w = gptr<T>(nullptr),
+                                           gptr<const T> R_ = gptr<const T>(nullptr),
+                                           gptr<T> fc = gptr<T>(nullptr)) {
+  constexpr int NZC = (NZ + 1) / 2;
   const cptr<T> Ds = as_const(Ds_);
   const cptr<T> sig = as_const(sig_);
+  const cptr<T> R = as_const(R_);
   const bool full = (mode == FIN_FULL);
   const bool apply = (mode == FIN_APPLY) || full;   // rows hold A in; otherwise f - A in
   for (int i = tid(); i < nx; i += nthr()) {
@@ -996,6 +1017,7 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> Ds_,
       }
 #pragma unroll
       for (int l = 0; l < NZ; ++l) out[l * nx + i] = res[l];
+      if (fc) col_restrict_regs<T, NZ>(nx, R, res, fc, i);
       if (mode == FIN_COLSTEP) {
         T xn[NZ];
 #pragma unroll
@@ -1041,12 +1063,13 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> Ds_,
           }
         }
       }
-      if (mode == FIN_COLSTEP) {
+      if (mode == FIN_COLSTEP || fc) {
         T r[NZ];
 #pragma unroll
         for (int l = 0; l < NZ; ++l) r[l] = out[l * nx + i];
+        if (fc) col_restrict_regs<T, NZ>(nx, R, r, fc, i);
 #pragma unroll 1
-        for (int j = 0; j < NZ; j += C) {
+        for (int j = 0; j < NZ && mode == FIN_COLSTEP; j += C) {
           T s[C], xo[C];
 #pragma unroll
           for (int q = 0; q < C; ++q) {
@@ -1061,7 +1084,7 @@ __device__ __forceinline__ void col_finish(int mode, int nx, gptr<const T> Ds_,
           for (int q = 0; q < C; ++q)
             if (j + q < NZ) x[(j + q) * nx + i] = xo[q] + omega * s[q];
         }
-        if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
+        if (mode == FIN_COLSTEP && t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
       }
     }
   }
@@ -1133,11 +1156,15 @@ __device__ void col_restrict(int nx, gptr<const T> R_, gptr<const T> r, gptr<T> 
   }
 }
 
-// x += P xc (prolongation from the next coarser order).
+// x += P xc (prolongation from the next coarser order). When t1w is non-null, also
+// t1w = D_s x for the corrected column (the next operator application then skips its D_s phase).
 template <typename T, int NZ>
-__device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr<T> x) {
+__device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr<T> x,
+                                gptr<const T> Ds_ = gptr<const T>(nullptr),
+                                gptr<T> t1w = gptr<T>(nullptr)) {
   constexpr int NZC = (NZ + 1) / 2;
   const cptr<T> P = as_const(P_);
+  const cptr<T> Ds = as_const(Ds_);
   for (int i = tid(); i < nx; i += nthr()) {
     T v[NZC];
 #pragma unroll
@@ -1146,13 +1173,16 @@ __device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr
       T xv[NZ];
 #pragma unroll
       for (int j = 0; j < NZ; ++j) xv[j] = x[j * nx + i];
+      T xn[NZ];
 #pragma unroll
       for (int j = 0; j < NZ; ++j) {
         T s = T(0);
 #pragma unroll
         for (int c = 0; c < NZC; ++c) s += P[j * NZC + c] * v[c];
-        x[j * nx + i] = xv[j] + s;
+        xn[j] = xv[j] + s;
+        x[j * nx + i] = xn[j];
       }
+      if (t1w) col_dsig_regs<T, NZ>(nx, Ds, xn, t1w, i);
     } else {
       constexpr int C = kRowChunk<T, NZ>;
 #pragma unroll 1
@@ -1171,6 +1201,7 @@ __device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr
         for (int q = 0; q < C; ++q)
           if (j + q < NZ) x[(j + q) * nx + i] = xo[q] + s[q];
       }
+      if (t1w) col_dsig_one<T, NZ>(nx, Ds, gptr<const T>(x), t1w, i);
     }
   }
 }
@@ -1189,7 +1220,7 @@ template <typename T, int NZ>
 __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int mode,
                                          gptr<const T> in, gptr<T> out, gptr<const T> f,
                                          gptr<T> x, T omega, bool t1_ready = false,
-                                         bool keep_t1 = false) {
+                                         bool keep_t1 = false, gptr<T> fc = gptr<T>(nullptr)) {
   const int nx = c.nx;
   const gptr<T> t1 = L.t1;
   const gptr<T> t2 = L.t2;
@@ -1198,7 +1229,9 @@ __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int m
   const Geo<T> g = c.g;
   if (!t1_ready) {
     col_dsig<T, NZ>(nx, L.Ds, in, t1);
-    __syncthreads();   // phase C reads t1
+    // the fused float32 passes read t1 without a barrier of their own; float64 runs B and C
+    // apart, and B's closing barrier orders t1 for C
+    if constexpr (sizeof(T) == 4) __syncthreads();
   }
   dx2_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
               [=](int j, int i) { return in[j * nx + i]; },
@@ -1207,7 +1240,7 @@ __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int m
               [=](int j, int i, T px) { return px + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i]; },
               [=](int j, int i, T v) { t3[j * nx + i] = v; });
   col_finish<T, NZ>(mode, nx, L.Ds, sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega,
-                    keep_t1 ? t1 : gptr<T>(nullptr));
+                    keep_t1 ? t1 : gptr<T>(nullptr), L.R, fc);
   __syncthreads();
 }
 
@@ -1319,9 +1352,9 @@ template <typename T, int NZ, bool TR>
 __device__ __forceinline__ void op_any(const Ctx<T>& c, const Lev<T>& L, int mode,
                                        gptr<const T> in, gptr<T> out, gptr<const T> f,
                                        gptr<T> x, T omega, bool t1_ready = false,
-                                       bool keep_t1 = false) {
+                                       bool keep_t1 = false, gptr<T> fc = gptr<T>(nullptr)) {
   if constexpr (TR) op_apply_T<T, NZ>(c, L, mode, in, out, f, x, omega);
-  else op_apply<T, NZ>(c, L, mode, in, out, f, x, omega, t1_ready, keep_t1);
+  else op_apply<T, NZ>(c, L, mode, in, out, f, x, omega, t1_ready, keep_t1, fc);
 }
 
 template <typename P>
@@ -1339,7 +1372,9 @@ __device__ __forceinline__ void fill_zero(P p, int n) {
 //   DOWN  residual, restriction, the coarser V-cycle (a call), prolongation and correction
 // in the order nu1 x (COL, MODE), DOWN, nu2 x (COL, MODE); the coarsest level (3 rows) runs
 // coarse_pairs x (COL, MODE). The operator appears once in the loop body, which keeps each
-// level's code compact.
+// level's code compact. In the forward cycle the residual phase before DOWN also restricts each
+// column it finishes, and the prolongation also leaves D_s x in t1, so neither runs as a phase of
+// its own behind a barrier.
 //
 // TR = true gives the transpose M^T of the cycle's linear map M (the preconditioner of the
 // adjoint solve): the same cycle on A^T with every step's order reversed (nu2 x (MODE, COL),
@@ -1369,9 +1404,15 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
     if (q < 2 * npre) kind = (q & 1) ? second : first;
     else if (NZ != 3 && q == 2 * npre) kind = DOWN;
     else kind = ((q - 2 * npre - 1) & 1) ? second : first;
+    // before a level move of the forward cycle the residual phase also restricts its columns
+    gptr<T> fc(nullptr);
+    if constexpr (NZ > 3 && !TR) {
+      if (kind == DOWN) fc = uni(lev(l + 1)).f;
+    }
     if (!xzero)
       op_any<T, NZ, TR>(c, L, kind == COL ? FIN_COLSTEP : FIN_RESID, L.x, L.r, L.f, L.x, wc,
-                        !TR && t1x, !TR && kind == COL);
+                        !TR && t1x, !TR && kind == COL, fc);
+    const bool restricted = !xzero && fc;
     t1x = !TR && kind == COL;
     if (kind == COL) {
       if (xzero) {
@@ -1393,12 +1434,17 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
         constexpr int NZC = (NZ + 1) / 2;
         const Lev<T> C = uni(lev(l + 1));
         if (xzero) fill_zero(L.x, NZ * nx);
-        col_restrict<T, NZ>(nx, TR ? L.PT : L.R,
-                            xzero ? gptr<const T>(L.f) : gptr<const T>(L.r), C.f);
-        __syncthreads();
+        if (!restricted) {
+          col_restrict<T, NZ>(nx, TR ? L.PT : L.R,
+                              xzero ? gptr<const T>(L.f) : gptr<const T>(L.r), C.f);
+          __syncthreads();
+        }
         vcycle<T, NZC, LP, TR>(c, lev, l + 1, o);
-        col_prolong_add<T, NZ>(nx, TR ? L.RT : L.P, C.x, L.x);
+        // forward cycle: the correction also leaves D_s x in t1 for the next step's operator
+        col_prolong_add<T, NZ>(nx, TR ? L.RT : L.P, C.x, L.x, TR ? gptr<const T>(nullptr) : L.Ds,
+                               TR ? gptr<T>(nullptr) : L.t1);
         __syncthreads();
+        t1x = !TR;
         xzero = false;
       }
     }
