@@ -202,8 +202,10 @@ int pmgw_adjoint_solve(pmgw_plan plan, const double* g, double* lambda, double r
  * ub, wb, etab, Kub, Kwb, Ketab: on entry the adjoints of the stage's outputs, on exit the
  * adjoints of its inputs (in place). hbar: adjoint of the depth h, ACCUMULATED (+=).
  * The call recomputes the stage's intermediates (including its pressure solve, to rtol) in the
- * workspace, then solves one adjoint system A^T lambda = pbar (pmgw_adjoint_solve, to rtol;
- * its info goes to info_dev when non-NULL). The forward solve is differentiated as exact.
+ * workspace, then solves one adjoint system A^T lambda = pbar (pmgw_adjoint_solve, to rtol).
+ * info_dev (device, nullable) holds 2 x ntanks records: entries [0, ntanks) receive the forward
+ * recompute solve's outcome per tank, entries [ntanks, 2 ntanks) the adjoint solve's. The forward
+ * solve is differentiated as exact.
  * The plan's geometry is left at the stage's (eta^(k-1), eta^(k)).
  */
 int rk4_stage_adjoint(pmgw_plan plan, int32_t k, double dt, const double* h, const double* u,

@@ -5,6 +5,9 @@ orders the calls and keeps checkpoints: the state at every `checkpoint`-th step 
 the forward run, and the reverse sweep recomputes the stage inputs of one segment at a time from
 its checkpoint (memory: n_steps/checkpoint + 5*checkpoint states instead of 5*n_steps).
 
+Every solve's outcome goes to a device info buffer that is read once per checkpoint segment; a
+solve that ends with a status other than OK (not converged, NaN) raises PmgwError.
+
 - `gradient(...)`: adjoint sweep for given adjoints of the final (u, w, eta); returns the
   gradient w.r.t. the depth h and the adjoints of the initial (u, w, eta).
 - `Rk4Steps`: the same as a torch.autograd.Function of (h, u0, w0, eta0).
@@ -27,27 +30,66 @@ def initial_state(u0, w0, eta0):
                 Keta=torch.zeros_like(eta0), p=z.clone())
 
 
-def stage(plan, k, dt, h, st, rtol, maxit=100):
+class _Infos:
+    """Device records of the solves of one checkpoint segment (one per stage and tank; two per
+    stage and tank for reverse stages: forward recompute, then adjoint). `check` reads them once
+    per segment and raises on any status other than OK, so that a NOCONV or ENAN solve inside the
+    stepping does not go unnoticed."""
+
+    def __init__(self, plan, stages, per_stage):
+        self.plan, self.per = plan, per_stage
+        self.buf = pmgw.info_buffer(plan.ntanks * stages * per_stage,
+                                    device=getattr(plan, "device", None))
+        self.n = 0
+
+    def next(self):
+        w = 2 * self.plan.ntanks * self.per
+        rec = self.buf[w * self.n: w * (self.n + 1)]
+        self.n += 1
+        return rec
+
+    def check(self, what):
+        if self.n == 0:
+            return
+        used = self.buf[: 2 * self.plan.ntanks * self.per * self.n]
+        for i, r in enumerate(pmgw.read_info(used)):
+            if r["status"] != pmgw.OK:
+                raise pmgw.PmgwError(r["status"], f"{what}: solve record {i} "
+                                                  f"(stage-call {i // (self.plan.ntanks * self.per)})"
+                                                  f" has status {r['status']}, relres "
+                                                  f"{r['relres']:.3e}")
+        self.buf.zero_()
+        self.n = 0
+
+
+def stage(plan, k, dt, h, st, rtol, maxit=100, info=None):
     pmgw.rk4_stage(plan, k, dt, h, st["u"], st["w"], st["eta"], st["Ku"], st["Kw"],
-                   st["Keta"], st["p"], rtol=rtol, maxit=maxit)
+                   st["Keta"], st["p"], rtol=rtol, maxit=maxit,
+                   info_dev=info.next() if info is not None else None)
 
 
 def run(plan, h, st, dt, nsteps, rtol=1e-12, checkpoint=None):
     """Advance st (in place) by nsteps; returns the list of checkpoints taken before steps
-    0, C, 2C, ... when checkpoint = C is given."""
+    0, C, 2C, ... when checkpoint = C is given. Every solve's status is checked once per
+    segment of C steps (or once at the end); a failed solve raises PmgwError."""
     cps = []
+    seg = checkpoint or nsteps
+    infos = _Infos(plan, 5 * max(1, min(seg, nsteps)), 1)
     for n in range(nsteps):
         if checkpoint and n % checkpoint == 0:
+            infos.check("forward stepping")
             cps.append(_clone(st))
         for k in range(1, 6):
-            stage(plan, k, dt, h, st, rtol)
+            stage(plan, k, dt, h, st, rtol, info=infos)
+    infos.check("forward stepping")
     return cps
 
 
 def gradient(plan, h, st0, dt, nsteps, bar_final, checkpoint=10, rtol=1e-12):
     """Reverse sweep. bar_final: dict with the adjoints of the final u, w, eta (K registers of
     the final state get zero adjoints). Returns (hbar, bar) where bar holds the adjoints of the
-    initial state's u, w, eta, Ku, Kw, Keta."""
+    initial state's u, w, eta, Ku, Kw, Keta. Every forward, recompute and adjoint solve is
+    checked once per checkpoint segment; a failed solve raises PmgwError."""
     st = _clone(st0)
     cps = run(plan, h, st, dt, nsteps, rtol, checkpoint)
     bar = {k: torch.zeros_like(st0[k]) for k in KEYS}
@@ -55,6 +97,8 @@ def gradient(plan, h, st0, dt, nsteps, bar_final, checkpoint=10, rtol=1e-12):
         if bar_final.get(k) is not None:
             bar[k].copy_(bar_final[k])
     hbar = torch.zeros_like(h)
+    fwd = _Infos(plan, 5 * checkpoint, 1)
+    rev = _Infos(plan, 5 * checkpoint, 2)
     for c in range(len(cps) - 1, -1, -1):
         first = c * checkpoint
         last = min(nsteps, first + checkpoint)
@@ -63,9 +107,12 @@ def gradient(plan, h, st0, dt, nsteps, bar_final, checkpoint=10, rtol=1e-12):
         for _ in range(first, last):
             for k in range(1, 6):
                 inputs.append((k, _clone(cur)))
-                stage(plan, k, dt, h, cur, rtol)
+                stage(plan, k, dt, h, cur, rtol, info=fwd)
         for k, sin in reversed(inputs):
-            pmgw.rk4_stage_adjoint(plan, k, dt, h, sin, bar, hbar, rtol=rtol)
+            pmgw.rk4_stage_adjoint(plan, k, dt, h, sin, bar, hbar, rtol=rtol,
+                                   info_dev=rev.next())
+        fwd.check(f"segment {c} recompute")
+        rev.check(f"segment {c} reverse stages")
     return hbar, bar
 
 

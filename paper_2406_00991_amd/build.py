@@ -1,11 +1,17 @@
 """Build the HIP library libpmgw.so in-tree for gfx950 (hipcc, no JIT cache).
 
-After compiling, the device code is also compiled to AMD assembly and checked: the build fails if
-any function contains a long-branch sequence (s_getpc/s_add/s_setpc to a label). In non-entry
+The library is compiled as several translation units in parallel: the host API (pmgw.hip), the
+solve kernels once per V-cycle precision and direction (pmgw_solve.hip), and the Runge-Kutta
+stage kernels and their adjoints (pmgw_stage.hip); the objects are linked into one shared
+library.
+
+Every compile keeps its device assembly (-save-temps), and the build checks it: it fails if any
+function contains a long-branch sequence (s_getpc/s_add/s_setpc to a label). In non-entry
 functions the compiler's long-branch expansion has been seen to use s[30:31], the register that
 holds the function's return address, which makes the function return into its own body. Keeping
 every function within the short-branch range rules that out.
 """
+import glob
 import os
 import re
 import subprocess
@@ -13,7 +19,7 @@ import sys
 import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "pmgw.hip")
+CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmgw.so")
 
 FLAGS = [
@@ -21,23 +27,24 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
+# (source, extra defines) of each translation unit
+UNITS = [
+    ("pmgw.hip", []),
+    ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=0"]),
+    ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=0"]),
+    ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=1"]),
+    ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=1"]),
+    ("pmgw_stage.hip", ["-DPMGW_STAGE_PART=0"]),
+    ("pmgw_stage.hip", ["-DPMGW_STAGE_PART=1"]),
+]
+
 
 def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def _asm_cmd(asm):
-    return [_hipcc(), *FLAGS, "--cuda-device-only", "-S", SRC, "-o", asm]
-
-
 def check_device_asm(verbose=False, asm_text=None):
-    """Compile the device code to assembly (unless given); return per-kernel resource usage.
-    Raises on long branches."""
-    if asm_text is None:
-        with tempfile.TemporaryDirectory() as td:
-            asm = os.path.join(td, "dev.s")
-            subprocess.run(_asm_cmd(asm), check=True, stderr=subprocess.DEVNULL)
-            asm_text = open(asm).read()
+    """Per-kernel resource usage from device assembly text. Raises on long branches."""
     text = asm_text
     if ".Lpost_getpc" in text:
         raise RuntimeError("device code contains long-branch sequences (s_getpc/s_setpc); "
@@ -56,28 +63,73 @@ def check_device_asm(verbose=False, asm_text=None):
     return stats
 
 
-def build(verbose=False, check=True):
-    """Compile the library and (concurrently) the device assembly for the check."""
+def build(verbose=False, check=True, jobs=None):
+    """Compile every translation unit in parallel (at most `jobs` at once), check the device
+    assembly, link. Returns the library path."""
+    jobs = jobs or min(len(UNITS), max(1, os.cpu_count() or 1), 16)
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), *FLAGS, "-fPIC", "-shared", SRC, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
     with tempfile.TemporaryDirectory() as td:
-        asm = os.path.join(td, "dev.s")
-        chk = subprocess.Popen(_asm_cmd(asm), stderr=subprocess.DEVNULL) if check else None
-        lib = subprocess.Popen(cmd)
-        rc_lib = lib.wait()
-        rc_chk = chk.wait() if chk else 0
-        if rc_lib != 0:
-            raise subprocess.CalledProcessError(rc_lib, cmd)
-        if rc_chk != 0:
-            raise subprocess.CalledProcessError(rc_chk, _asm_cmd(asm))
+        procs, objs, dirs = [], [], []
+        pending = list(enumerate(UNITS))
+        running = []
+        while pending or running:
+            while pending and len(running) < jobs:
+                i, (src, defs) = pending.pop(0)
+                wd = os.path.join(td, f"u{i}")
+                os.makedirs(wd)
+                obj = os.path.join(wd, f"u{i}.o")
+                cmd = [_hipcc(), *FLAGS, *defs, "-fPIC", "-c"]
+                if check:
+                    cmd.append("-save-temps")
+                cmd += [os.path.join(CSRC, src), "-o", obj]
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+                running.append((cmd, subprocess.Popen(cmd, cwd=wd, stderr=subprocess.PIPE)))
+                objs.append(obj)
+                dirs.append(wd)
+            cmd, pr = running.pop(0)
+            _, err = pr.communicate()
+            if pr.returncode != 0:
+                for _, q in running:
+                    q.kill()
+                sys.stderr.write(err.decode(errors="replace"))
+                raise subprocess.CalledProcessError(pr.returncode, cmd)
         if check:
-            check_device_asm(verbose, open(asm).read())
+            text = ""
+            for wd in dirs:
+                for s in glob.glob(os.path.join(wd, "*amdgcn-amd-amdhsa*gfx950*.s")):
+                    text += open(s).read()
+            if not text:
+                raise RuntimeError("no device assembly found for the long-branch check")
+            check_device_asm(verbose, text)
+        link = [_hipcc(), *FLAGS, "-fPIC", "-shared", *objs, "-o", tmp]
+        lk = subprocess.run(link, stderr=subprocess.PIPE)
+        if lk.returncode != 0:
+            sys.stderr.write(lk.stderr.decode(errors="replace"))
+            raise subprocess.CalledProcessError(lk.returncode, link)
     os.replace(tmp, LIB)
     return LIB
 
 
+def device_stats(verbose=True):
+    """Build with the assembly kept and print per-kernel VGPR / spill / scratch / LDS use."""
+    stats = {}
+    with tempfile.TemporaryDirectory() as td:
+        for i, (src, defs) in enumerate(UNITS):
+            asm = os.path.join(td, f"u{i}.s")
+            subprocess.run([_hipcc(), *FLAGS, *defs, "--cuda-device-only", "-S",
+                            os.path.join(CSRC, src), "-o", asm], check=True,
+                           stderr=subprocess.DEVNULL)
+            stats.update(check_device_asm(False, open(asm).read()))
+    if verbose:
+        for k, v in sorted(stats.items()):
+            print(f"  {k[:70]:70s} {v}")
+    return stats
+
+
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv, check="--no-check" not in sys.argv)
-    print(LIB)
+    if "--stats" in sys.argv:
+        device_stats()
+    else:
+        build(verbose="-v" in sys.argv, check="--no-check" not in sys.argv)
+        print(LIB)

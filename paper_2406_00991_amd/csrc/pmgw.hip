@@ -10,9 +10,8 @@
 #include <vector>
 
 #include "../../include/pmgw.h"
-#include "pmgw_kernels.hpp"
-#include "pmgw_rk.hpp"
-#include "pmgw_rka.hpp"
+#include "pmgw_launch.hpp"
+#include "pmgw_setup.hpp"
 
 using namespace pmgw;
 
@@ -241,9 +240,6 @@ size_t lds_bytes(int fftb, int maxnx) { return (size_t)(2 * fftb) + (size_t)24 *
 
 int nz_class(int nz) { return nz == 3 ? 0 : nz == 5 ? 1 : nz == 9 ? 2 : nz == 17 ? 3 : 4; }
 
-// Largest workgroup the solve kernel is compiled for (its register budget follows from it).
-constexpr int kSolveMaxThreads = 256;
-
 // Bytes of one FFT half for a solve launch. Classes whose rows all go through the wavefront FFT
 // (64 <= Nx <= 512) get what kWaveRows row pairs per wavefront need (2 fftb = wavefronts x
 // kWaveRows x Nx complex float64), so that with fewer threads per workgroup two workgroups fit in
@@ -259,15 +255,21 @@ int solve_fftb(int threads, int maxnx) {
 template <typename TV, int NZ, bool TR>
 void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, double rtol,
                   int maxit, pmgw_info_dev* info, const KOpts& o, hipStream_t st) {
-  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
-  const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
-  const int nt = (int)p->ids[c].size();
-  constexpr int MAXT = kSolveMaxThreads;
-  const int thr = p->opts.threads ? p->opts.threads : MAXT;
-  const int fftb = solve_fftb(thr, p->maxnx[c]);
-  hipLaunchKernelGGL((k_solve<TV, NZ, MAXT, TR>), dim3((unsigned)nt), dim3(thr),
-                     lds_bytes(fftb, p->maxnx[c]), st, d, ids, p->ws, mode, in, out, rtol, maxit,
-                     info, o, fftb);
+  SolveArgs a;
+  a.descs = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  a.ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
+  a.ws = p->ws;
+  a.mode = mode;
+  a.in = in;
+  a.out = out;
+  a.rtol = rtol;
+  a.maxit = maxit;
+  a.info = info;
+  a.o = o;
+  const int thr = p->opts.threads ? p->opts.threads : 256;
+  a.fftb = solve_fftb(thr, p->maxnx[c]);
+  launch_k_solve<TV, NZ, TR>((unsigned)p->ids[c].size(), thr, lds_bytes(a.fftb, p->maxnx[c]), st,
+                             a);
 }
 
 // Creates the side streams and fork/join events once (only plans with several Nz classes).
@@ -798,19 +800,23 @@ template <int NZ>
 void launch_rk(pmgw_plan p, int c, int which, const RkCoef& cf, const double* u, const double* w,
                double* eta, double* Ku, double* Kw, double* Keta, const double* pr, double* uo,
                double* wo, const RkBufs& rb) {
-  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
-  const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
-  const unsigned nt = (unsigned)p->ids[c].size();
-  const int fftb = 32768;
-  if (which == 0)
-    hipLaunchKernelGGL(k_rk_pre<NZ>, dim3(nt), dim3(256), lds_bytes(fftb, p->maxnx[c]), p->stream, d, ids,
-                       p->ws, cf, u, w, eta, Keta, rb, fftb);
-  else if (which == 1)
-    hipLaunchKernelGGL(k_rk_force<NZ>, dim3(nt), dim3(256), lds_bytes(fftb, p->maxnx[c]), p->stream, d, ids,
-                       p->ws, cf, u, w, (const double*)Ku, (const double*)Kw, rb, fftb);
-  else
-    hipLaunchKernelGGL(k_rk_post<NZ>, dim3(nt), dim3(256), lds_bytes(fftb, p->maxnx[c]), p->stream, d, ids,
-                       p->ws, cf, pr, uo, wo, Ku, Kw, rb, fftb);
+  RkArgs a;
+  a.descs = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  a.ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
+  a.ws = p->ws;
+  a.cf = cf;
+  a.u = u;
+  a.w = w;
+  a.eta = eta;
+  a.Ku = Ku;
+  a.Kw = Kw;
+  a.Keta = Keta;
+  a.pr = pr;
+  a.uo = uo;
+  a.wo = wo;
+  a.rb = rb;
+  a.fftb = 32768;
+  launch_k_rk<NZ>(which, (unsigned)p->ids[c].size(), lds_bytes(a.fftb, p->maxnx[c]), p->stream, a);
 }
 
 int launch_rk_all(pmgw_plan p, int which, const RkCoef& cf, double* u, double* w, double* eta,
@@ -866,23 +872,25 @@ template <int NZ>
 void launch_rka(pmgw_plan p, int c, int which, const RkCoef& cf, const double* u,
                 const double* w, double* ub, double* wb, double* etab, double* Kub, double* Kwb,
                 double* Ketab, double* hbar, const RkBufs& rb, const AdjBufs& ab) {
-  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
-  const int32_t* ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
-  const unsigned nt = (unsigned)p->ids[c].size();
-  const int fftb = 32768;
-  const size_t lds = lds_bytes(fftb, p->maxnx[c]);
-  if (which == 0)
-    hipLaunchKernelGGL(k_rka_post<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
-                       ub, wb, Kub, Kwb, rb, ab, fftb);
-  else if (which == 1)
-    hipLaunchKernelGGL(k_rka_mid<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
-                       ub, wb, Kub, Kwb, rb, ab, fftb);
-  else if (which == 2)
-    hipLaunchKernelGGL(k_rka_force<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
-                       u, w, ub, wb, rb, ab, fftb);
-  else
-    hipLaunchKernelGGL(k_rka_pre<NZ>, dim3(nt), dim3(256), lds, p->stream, d, ids, p->ws, cf,
-                       u, ub, wb, etab, Ketab, hbar, rb, ab, fftb);
+  RkaArgs a;
+  a.descs = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  a.ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
+  a.ws = p->ws;
+  a.cf = cf;
+  a.u = u;
+  a.w = w;
+  a.ub = ub;
+  a.wb = wb;
+  a.etab = etab;
+  a.Kub = Kub;
+  a.Kwb = Kwb;
+  a.Ketab = Ketab;
+  a.hbar = hbar;
+  a.rb = rb;
+  a.ab = ab;
+  a.fftb = 32768;
+  launch_k_rka<NZ>(which, (unsigned)p->ids[c].size(), lds_bytes(a.fftb, p->maxnx[c]), p->stream,
+                   a);
 }
 
 int launch_rka_all(pmgw_plan p, int which, const RkCoef& cf, const double* u, const double* w,
@@ -949,8 +957,11 @@ extern "C" int rk4_stage_adjoint(pmgw_plan p, int32_t k, double dt, const double
   if (rc) return rc;
   rc = launch_rk_all(p, 1, cf, cu, cw, ab.eta1, cku, ckw, ab.keta1, nullptr, rb);
   if (rc) return rc;
-  pmgw_info_dev* iinfo = reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
-  pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev) : iinfo;
+  // info_dev, when given, holds 2 x ntanks records: the forward recompute solve's, then the
+  // adjoint solve's
+  pmgw_info_dev* iinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev)
+                                  : reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
+  pmgw_info_dev* dinfo = info_dev ? iinfo + p->ntanks : iinfo;
   if ((rc = fill_zero_dev(p, ab.p, n2d))) return rc;
   rc = launch_solve(p, MODE_SOLVE, rb.b, ab.p, rtol, maxit, iinfo);
   if (rc) return rc;

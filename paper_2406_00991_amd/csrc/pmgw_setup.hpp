@@ -1,0 +1,222 @@
+// Set-up kernels of the p-multigrid Poisson library, launched only by the host API: a fill
+// kernel, the geometry/metrics kernel and the block-inversion kernel.
+#pragma once
+#include "pmgw_kernels.hpp"
+
+namespace pmgw {
+
+// a[e] = v for e < n (grid-stride).
+__global__ void __launch_bounds__(256) k_fill(double* a, int64_t n, double v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    a[e] = v;
+}
+
+// ----------------------------------------------------------------------------- geometry kernel
+
+constexpr int kGeoFftBytes = 32768;   // the geometry kernel: 2 x 32 KB of FFT LDS + twiddles
+//
+// One workgroup per tank: copies h, eta_old, eta_new, checks d > 0, and forms the
+// sigma-metrics of paper eq. 1_Scoef for both geometries: sigma_x = a + b sigma with
+// a = h_x / d, b = -d_x / d, and 1/d; h_x and d_x by the FFT derivative. Also the x-averages
+// cbar = <1/(d_o d_n)> and ebar = <(1 + h_x^2)/d_o> of the flat-mode operator, the mode-step
+// damping factor min(1, 2 / (1 + (r/2)^0.4)) with r = max c / min c, c = 1/(d_o d_n), and float32
+// copies for mixed plans.
+__global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ descs, char* ws,
+                                                  const double* h, const double* eo,
+                                                  const double* en) {
+  __shared__ double red[16];
+  const TankDesc td = descs[blockIdx.x];
+  const int nx = td.nx;
+  if (nx < 8 || nx > 2048) return;
+  double* G = mp<double>(ws, td.geo64);
+  const double* hh = h + td.off1d;
+  const double* e0 = eo + td.off1d;
+  const double* e1 = en + td.off1d;
+  int bad = 0;
+  for (int i = tid(); i < nx; i += nthr()) {
+    const double a = hh[i], b = e0[i], c = e1[i];
+    G[GEO_H * nx + i] = a;
+    G[GEO_EO * nx + i] = b;
+    G[GEO_EN * nx + i] = c;
+    const double d0 = a + b, d1 = a + c;
+    if (!(d0 > 0.0) || !(d1 > 0.0) || !isfinite(d0) || !isfinite(d1)) bad = 1;
+  }
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx,
+                 kGeoFftBytes);
+  // rows: 0 = h, 1 = d_old, 2 = d_new  ->  h_x (GEO_HX), d_x old (GEO_BO), d_x new (GEO_BN)
+  dx_rows<double>(3, nx, td.log2nx, td.kfac, kGeoFftBytes,
+                  [=](int j, int i) {
+                    return j == 0 ? G[GEO_H * nx + i]
+                                  : G[GEO_H * nx + i] + G[(j == 1 ? GEO_EO : GEO_EN) * nx + i];
+                  },
+                  [=](int j, int i, double v) {
+                    G[(j == 0 ? GEO_HX : (j == 1 ? GEO_BO : GEO_BN)) * nx + i] = v;
+                  });
+  double sc = 0.0, se = 0.0, cmax = 0.0, icmax = 0.0;
+  float* G32 = mp<float>(ws, td.geo32);
+  for (int i = tid(); i < nx; i += nthr()) {
+    const double hx = G[GEO_HX * nx + i];
+    const double ido = 1.0 / (G[GEO_H * nx + i] + G[GEO_EO * nx + i]);
+    const double idn = 1.0 / (G[GEO_H * nx + i] + G[GEO_EN * nx + i]);
+    const double ao = hx * ido, bo = -G[GEO_BO * nx + i] * ido;
+    const double an = hx * idn, bn = -G[GEO_BN * nx + i] * idn;
+    G[GEO_AO * nx + i] = ao; G[GEO_BO * nx + i] = bo; G[GEO_IDO * nx + i] = ido;
+    G[GEO_AN * nx + i] = an; G[GEO_BN * nx + i] = bn; G[GEO_IDN * nx + i] = idn;
+    G32[i] = (float)ao; G32[nx + i] = (float)bo; G32[2 * nx + i] = (float)ido;
+    G32[3 * nx + i] = (float)an; G32[4 * nx + i] = (float)bn; G32[5 * nx + i] = (float)idn;
+    G32[6 * nx + i] = (float)hx;
+    sc += ido * idn;
+    se += (1.0 + hx * hx) * ido;
+    cmax = fmax(cmax, fabs(ido * idn));
+    icmax = fmax(icmax, 1.0 / fabs(ido * idn));
+  }
+  sc = block_sum(sc, red);
+  se = block_sum(se, red);
+  cmax = block_max(cmax, red);
+  icmax = block_max(icmax, red);
+  const double nb = block_sum((double)bad, red);
+  if (tid() == 0) {
+    double* S = mp<double>(ws, td.scal);
+    S[0] = sc / nx;
+    S[1] = se / nx;
+    *reinterpret_cast<int32_t*>(S + 2) = nb > 0.0 ? ST_EGEOM : ST_OK;
+    // mode-step damping: r = max c / min c with c = 1/(d_o d_n); min(1, 2 / (1 + (r/2)^0.4))
+    const double r = cmax * icmax;
+    S[3] = fmin(1.0, 2.0 / (1.0 + pow(0.5 * r, 0.4)));
+  }
+}
+
+// ----------------------------------------------------------------------------- block kernel
+//
+// One 64-thread workgroup per block. Builds, in float64, either the column block B_i (the
+// x-diagonal block of the level operator at column i: interior rows
+// cxx I + diag(sx_n) D_s diag(sx_o) D_s + D_s^2/(d_n d_o), row 0 = e_0, bed row
+// -(h_x sx_o[M] + 1/d_o) (D_s)_M) or the flat-mode block of mode k (interior
+// -kappa_k^2 I + cbar D_s^2, row 0 = e_0, bed row -ebar (D_s)_M), inverts it by Gauss-Jordan
+// with partial pivoting in LDS, and stores the inverse in the plan's V-cycle precision.
+template <typename TV>
+__global__ void __launch_bounds__(64) k_blocks(const TankDesc* __restrict__ descs,
+                                               const BlockJob* __restrict__ jobs, int njobs,
+                                               char* ws) {
+  __shared__ double A[kMaxNz][kMaxNz + 1];
+  __shared__ double Dsl[kMaxNz][kMaxNz + 1];
+  __shared__ int piv[kMaxNz];
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first <= b) lo = mid; else hi = mid - 1;
+  }
+  const BlockJob jb = jobs[lo];
+  const int idx = (int)(b - jb.first);
+  const TankDesc& td = descs[jb.tank];
+  const LevelDesc& ld = td.lev[jb.level];
+  const int nz = ld.nz, M = nz - 1, nx = td.nx;
+  if (nz < 3 || nz > kMaxNz || nx < 8 || nx > 2048 || idx < 0 || idx > nx) return;
+  const int t = tid();
+  const double* Ds = cp<double>(ws, ld.ds[0]);
+  const double* sig = cp<double>(ws, ld.sig[0]);
+  for (int e = t; e < nz * nz; e += 64) Dsl[e / nz][e % nz] = Ds[e];
+  __syncthreads();
+  if (jb.kind == 0) {
+    const double* G = cp<double>(ws, td.geo64);
+    const int i = idx;
+    const double ao = G[GEO_AO * nx + i], bo = G[GEO_BO * nx + i], ido = G[GEO_IDO * nx + i];
+    const double an = G[GEO_AN * nx + i], bn = G[GEO_BN * nx + i], idn = G[GEO_IDN * nx + i];
+    const double hx = G[GEO_HX * nx + i];
+    if (t < nz) {
+      const int j = t;
+      const double sxn = an + bn * sig[j];
+      const double bedc = -(hx * (ao + bo * sig[M]) + ido);
+      for (int c = 0; c < nz; ++c) {
+        double v;
+        if (j == 0) {
+          v = (c == 0) ? 1.0 : 0.0;
+        } else if (j == M) {
+          v = bedc * Dsl[M][c];
+        } else {
+          double s = 0.0;
+          for (int m = 0; m < nz; ++m)
+            s += Dsl[j][m] * Dsl[m][c] * (sxn * (ao + bo * sig[m]) + idn * ido);
+          v = s + ((c == j) ? td.cxx : 0.0);
+        }
+        A[j][c] = v;
+      }
+    }
+  } else {
+    const double* S = cp<double>(ws, td.scal);
+    const double cbar = S[0], ebar = S[1];
+    const int k = idx;
+    const double kap = (k == nx / 2) ? 0.0 : td.kfac * (double)k;
+    if (t < nz) {
+      const int j = t;
+      for (int c = 0; c < nz; ++c) {
+        double v;
+        if (j == 0) {
+          v = (c == 0) ? 1.0 : 0.0;
+        } else if (j == M) {
+          v = -ebar * Dsl[M][c];
+        } else {
+          double s = 0.0;
+          for (int m = 0; m < nz; ++m) s += Dsl[j][m] * Dsl[m][c];
+          v = cbar * s - ((c == j) ? kap * kap : 0.0);
+        }
+        A[j][c] = v;
+      }
+    }
+  }
+  __syncthreads();
+  // In-place Gauss-Jordan inversion with row pivoting; thread t owns row t (or column t).
+  for (int k = 0; k < nz; ++k) {
+    // pivot: largest |A[t][k]| over t in [k, nz); NaN ranks highest so that every lane agrees
+    double v = -1.0;
+    if (t >= k && t < nz) {
+      v = fabs(A[t][k]);
+      if (!(v >= 0.0)) v = INFINITY;
+    }
+    int id = t;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v, o, 64);
+      const int oi = __shfl_xor(id, o, 64);
+      if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
+    }
+    const int p = min(max(id, k), nz - 1);
+    if (p != k && t < nz) {
+      const double tmp = A[k][t];
+      A[k][t] = A[p][t];
+      A[p][t] = tmp;
+    }
+    if (t == 0) piv[k] = p;
+    __syncthreads();
+    const double inv = 1.0 / A[k][k];
+    if (t < nz && t != k) {
+      const double fr = A[t][k] * inv;
+      for (int c = 0; c < nz; ++c)
+        if (c != k) A[t][c] -= fr * A[k][c];
+      A[t][k] = -fr;
+    }
+    __syncthreads();
+    if (t < nz) A[k][t] = (t == k) ? inv : A[k][t] * inv;
+    __syncthreads();
+  }
+  for (int k = nz - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k && t < nz) {
+      const double tmp = A[t][k];
+      A[t][k] = A[t][p];
+      A[t][p] = tmp;
+    }
+    __syncthreads();
+  }
+  if (jb.kind == 0) {
+    TV* out = mp<TV>(ws, ld.colinv);
+    for (int e = t; e < nz * nz; e += 64) out[(int64_t)e * nx + idx] = (TV)A[e / nz][e % nz];
+  } else {
+    const int nh = nx / 2 + 1;
+    TV* out = mp<TV>(ws, ld.modeinv);
+    for (int e = t; e < nz * nz; e += 64) out[(int64_t)e * nh + idx] = (TV)A[e / nz][e % nz];
+  }
+}
+
+}  // namespace pmgw

@@ -1,0 +1,36 @@
+// Instantiates the per-tank solve kernel for one V-cycle precision (PMGW_TV: float or double) and
+// one direction (PMGW_TR: 0 = A and the V-cycle, 1 = A^T and the transposed cycle), for every
+// finest-level row count. The build compiles this file once per combination, in parallel.
+#include "pmgw_launch.hpp"
+
+#ifndef PMGW_TV
+#error "PMGW_TV must be defined (float or double)"
+#endif
+#ifndef PMGW_TR
+#error "PMGW_TR must be defined (0 or 1)"
+#endif
+
+namespace pmgw {
+
+// Largest workgroup the solve kernel is compiled for (its register budget follows from it).
+constexpr int kSolveMaxThreads = 256;
+
+template <typename TV, int NZ, bool TR>
+void launch_k_solve(unsigned grid, int threads, size_t lds, hipStream_t st, const SolveArgs& a) {
+  hipLaunchKernelGGL((k_solve<TV, NZ, kSolveMaxThreads, TR>), dim3(grid), dim3(threads), lds, st,
+                     a.descs, a.ids, a.ws, a.mode, a.in, a.out, a.rtol, a.maxit, a.info, a.o,
+                     a.fftb);
+}
+
+template void launch_k_solve<PMGW_TV, 3, PMGW_TR != 0>(unsigned, int, size_t, hipStream_t,
+                                                        const SolveArgs&);
+template void launch_k_solve<PMGW_TV, 5, PMGW_TR != 0>(unsigned, int, size_t, hipStream_t,
+                                                        const SolveArgs&);
+template void launch_k_solve<PMGW_TV, 9, PMGW_TR != 0>(unsigned, int, size_t, hipStream_t,
+                                                        const SolveArgs&);
+template void launch_k_solve<PMGW_TV, 17, PMGW_TR != 0>(unsigned, int, size_t, hipStream_t,
+                                                         const SolveArgs&);
+template void launch_k_solve<PMGW_TV, 33, PMGW_TR != 0>(unsigned, int, size_t, hipStream_t,
+                                                         const SolveArgs&);
+
+}  // namespace pmgw

@@ -114,15 +114,45 @@ def default_opts(**kw):
     return o
 
 
-def _ptr(t, dtype=None):
+def _ptr(t, dtype=None, numel=None, device=None):
+    """Device address of a tensor after checking what the C ABI cannot: dtype, element count
+    (the library takes no lengths, so a short field would be read or written past its end),
+    contiguity and device. Raises PmgwError(EINVAL) before any library call."""
+    return _ptrs([(t, dtype, numel)], device)[0]
+
+
+def _ptrs(items, device=None):
+    """_ptr for several tensors: every shape check of every tensor runs before the device checks,
+    so a wrong length is reported as such whatever the order of the arguments."""
+    for t, dtype, numel in items:
+        if t is None:
+            continue
+        if dtype is not None and t.dtype != dtype:
+            raise PmgwError(EINVAL, f"tensor must be {dtype}, got {t.dtype}")
+        if numel is not None and t.numel() != numel:
+            raise PmgwError(EINVAL, f"tensor must have {numel} elements, got {t.numel()}")
+        if not t.is_contiguous():
+            raise PmgwError(EINVAL, "tensor must be contiguous")
+    out = []
+    for t, _, _ in items:
+        if t is None:
+            out.append(None)
+            continue
+        if not t.is_cuda:
+            raise PmgwError(EINVAL, "tensor must be on the GPU")
+        if device is not None and t.device.index != device:
+            raise PmgwError(EINVAL, f"tensor must be on cuda:{device}, got {t.device}")
+        out.append(ctypes.c_void_p(t.data_ptr()))
+    return out
+
+
+def _fields(plan, *spec):
+    """Pointers for (tensor, kind) pairs of one call: kind 2 = packed 2D field (off2d[-1]
+    float64), 1 = packed 1D field (off1d[-1] float64), 'i1' / 'i2' = an info buffer of one or two
+    records per tank (or None)."""
     import torch
-    if not t.is_cuda:
-        raise PmgwError(EINVAL, "tensor must be on the GPU")
-    if not t.is_contiguous():
-        raise PmgwError(EINVAL, "tensor must be contiguous")
-    if dtype is not None and t.dtype != dtype:
-        raise PmgwError(EINVAL, f"tensor must be {dtype}")
-    return ctypes.c_void_p(t.data_ptr())
+    size = {2: plan.n2d, 1: plan.n1d, "i1": 2 * plan.ntanks, "i2": 4 * plan.ntanks}
+    return _ptrs([(t, torch.float64, size[k]) for t, k in spec], plan.device_index)
 
 
 class Plan:
@@ -166,6 +196,10 @@ class Plan:
         self.n1d = self.off1d[-1]
         self.workspace_bytes = int(lib().pmgw_workspace_bytes(h))
         self.device = device if device is not None else "cuda"
+        self.device_index = None
+        if torch.cuda.is_available():
+            dv = torch.device(self.device)
+            self.device_index = dv.index if dv.index is not None else torch.cuda.current_device()
         self.ws = None
         if allocate:
             self.bind(torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device))
@@ -173,7 +207,7 @@ class Plan:
 
     def bind(self, ws):
         self.ws = ws
-        _check(lib().pmgw_bind_workspace(self._h, _ptr(ws), ws.numel()))
+        _check(lib().pmgw_bind_workspace(self._h, _ptr(ws, device=self.device_index), ws.numel()))
 
     def __del__(self):
         try:
@@ -198,12 +232,9 @@ class Plan:
     def set_geometry(self, h, eta_old, eta_new=None):
         import torch
         eta_new = eta_old if eta_new is None else eta_new
-        for t in (h, eta_old, eta_new):
-            if t.numel() != self.n1d:
-                raise PmgwError(EINVAL, "1D fields must have off1d[-1] entries")
         self._geo = (h, eta_old, eta_new)
-        _check(lib().pmgw_set_geometry(self._h, _ptr(h, torch.float64), _ptr(eta_old, torch.float64),
-                                       _ptr(eta_new, torch.float64)))
+        _check(lib().pmgw_set_geometry(self._h, *_fields(self, (h, 1), (eta_old, 1),
+                                                         (eta_new, 1))))
         _trace("set_geometry")
 
     def apply(self, p, out=None):
@@ -224,19 +255,19 @@ class Plan:
 
 def laplacian_apply(plan, p, Ap):
     import torch
-    _check(lib().laplacian_apply(plan._h, _ptr(p, torch.float64), _ptr(Ap, torch.float64)))
+    _check(lib().laplacian_apply(plan._h, *_fields(plan, (p, 2), (Ap, 2))))
     _trace("laplacian_apply")
 
 
 def pmg_vcycle(plan, r, z):
     import torch
-    _check(lib().pmg_vcycle(plan._h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
+    _check(lib().pmg_vcycle(plan._h, *_fields(plan, (r, 2), (z, 2))))
     _trace("pmg_vcycle")
 
 
 def fmg(plan, r, z):
     import torch
-    _check(lib().pmgw_fmg(plan._h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
+    _check(lib().pmgw_fmg(plan._h, *_fields(plan, (r, 2), (z, 2))))
     _trace("pmgw_fmg")
 
 
@@ -252,22 +283,21 @@ def adjoint_solve(plan, g, lam, rtol=1e-10, maxit=100, sync=True, info_dev=None)
 
 def adjoint_apply(plan, lam, out):
     import torch
-    _check(lib().pmgw_adjoint_apply(plan._h, _ptr(lam, torch.float64), _ptr(out, torch.float64)))
+    _check(lib().pmgw_adjoint_apply(plan._h, *_fields(plan, (lam, 2), (out, 2))))
     _trace("pmgw_adjoint_apply")
 
 
 def adjoint_vcycle(plan, r, z):
     import torch
-    _check(lib().pmgw_adjoint_vcycle(plan._h, _ptr(r, torch.float64), _ptr(z, torch.float64)))
+    _check(lib().pmgw_adjoint_vcycle(plan._h, *_fields(plan, (r, 2), (z, 2))))
     _trace("pmgw_adjoint_vcycle")
 
 
 def _solve(name, plan, b, p, rtol, maxit, sync, info_dev):
     import torch
+    bp, pp, dptr = _fields(plan, (b, 2), (p, 2), (info_dev, "i1"))
     infos = (Info * plan.ntanks)() if sync else None
-    dptr = _ptr(info_dev) if info_dev is not None else None
-    rc = getattr(lib(), name)(plan._h, _ptr(b, torch.float64), _ptr(p, torch.float64),
-                              float(rtol), int(maxit), infos, dptr)
+    rc = getattr(lib(), name)(plan._h, bp, pp, float(rtol), int(maxit), infos, dptr)
     _trace(name)
     if rc < 0:
         msg = lib().pmgw_last_error().decode()
@@ -286,27 +316,23 @@ def _solve(name, plan, b, p, rtol, maxit, sync, info_dev):
 
 def rk4_stage(plan, k, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10, maxit=100, info_dev=None):
     """One stage k (1..5) of the low-storage RK scheme with the pressure projection, in place."""
-    import torch
-    f64 = torch.float64
-    dptr = _ptr(info_dev) if info_dev is not None else None
-    _check(lib().rk4_stage(plan._h, int(k), float(dt), _ptr(h, f64), _ptr(u, f64), _ptr(w, f64),
-                           _ptr(eta, f64), _ptr(Ku, f64), _ptr(Kw, f64), _ptr(Keta, f64),
-                           _ptr(p, f64), float(rtol), int(maxit), dptr))
+    *args, dptr = _fields(plan, (h, 1), (u, 2), (w, 2), (eta, 1), (Ku, 2), (Kw, 2), (Keta, 1),
+                          (p, 2), (info_dev, "i1"))
+    _check(lib().rk4_stage(plan._h, int(k), float(dt), *args, float(rtol), int(maxit), dptr))
     _trace("rk4_stage")
 
 
 def rk4_stage_adjoint(plan, k, dt, h, state, bar, hbar, rtol=1e-12, maxit=200, info_dev=None):
     """Reverse of stage k. state: dict u, w, eta, Ku, Kw, Keta of the stage's INPUT state (left
     unchanged). bar: dict of the same keys holding the adjoints of the stage's outputs, replaced
-    in place by the adjoints of its inputs. hbar is accumulated."""
-    import torch
-    f64 = torch.float64
+    in place by the adjoints of its inputs. hbar is accumulated. info_dev (optional, 2 x ntanks
+    records): the forward recompute solve's record per tank, then the adjoint solve's."""
     keys = ("u", "w", "eta", "Ku", "Kw", "Keta")
-    dptr = _ptr(info_dev) if info_dev is not None else None
-    _check(lib().rk4_stage_adjoint(plan._h, int(k), float(dt), _ptr(h, f64),
-                                   *[_ptr(state[q], f64) for q in keys],
-                                   *[_ptr(bar[q], f64) for q in keys], _ptr(hbar, f64),
-                                   float(rtol), int(maxit), dptr))
+    kind = lambda q: 1 if q in ("eta", "Keta") else 2
+    *args, dptr = _fields(plan, (h, 1), *[(state[q], kind(q)) for q in keys],
+                          *[(bar[q], kind(q)) for q in keys], (hbar, 1), (info_dev, "i2"))
+    _check(lib().rk4_stage_adjoint(plan._h, int(k), float(dt), *args, float(rtol), int(maxit),
+                                   dptr))
     _trace("rk4_stage_adjoint")
 
 
@@ -331,14 +357,15 @@ def profile_read(plan):
 
 
 def info_buffer(ntanks, device=None):
-    """Device array of ntanks pmgw_info records (16 bytes each) for the info_dev arguments."""
+    """Device array of ntanks pmgw_info records (16 bytes each) for the info_dev arguments
+    (2 float64 slots per record; a record slice is buf[2 r: 2 (r + n)])."""
     import torch
     return torch.zeros(ntanks * 2, dtype=torch.float64, device=device or "cuda")
 
 
 def read_info(buf):
     """Synchronously read an info_buffer: list of dicts (iters, status, relres) per tank."""
-    import torch
-    raw = buf.cpu().numpy().view(np.int32).reshape(-1, 4)
-    rel = buf.cpu().numpy().reshape(-1, 2)[:, 1]
+    host = buf.cpu().numpy()
+    raw = host.view(np.int32).reshape(-1, 4)
+    rel = host.reshape(-1, 2)[:, 1]
     return [dict(iters=int(r[0]), status=int(r[1]), relres=float(x)) for r, x in zip(raw, rel)]

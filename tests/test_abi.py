@@ -80,3 +80,35 @@ def test_null_plan():
     L = pmgw.lib()
     assert L.laplacian_apply(None, None, None) == pmgw.EINVAL
     assert L.pmgw_workspace_bytes(None) == 0
+
+
+def test_binding_rejects_short_and_mistyped_tensors():
+    """The C ABI takes no lengths, so the binding checks every tensor's element count and dtype
+    before the call: a field shorter than the plan's packed size (or an info buffer shorter than
+    its records) is refused with EINVAL and never reaches the kernels."""
+    import torch
+    plan = pmgw.Plan([32, 64], [9, 17], [1.0, 2.0], allocate=False)
+    n2, n1 = plan.n2d, plan.n1d
+    f2 = lambda n=n2, dt=torch.float64: torch.zeros(n, dtype=dt)
+    f1 = lambda n=n1: torch.zeros(n, dtype=torch.float64)
+    calls = [
+        lambda: pmgw.poisson_solve(plan, f2(n2 - 1), f2()),
+        lambda: pmgw.poisson_solve(plan, f2(), f2(n2 - 8)),
+        lambda: pmgw.poisson_solve(plan, f2(), f2(), info_dev=f1(2 * plan.ntanks - 1)),
+        lambda: pmgw.laplacian_apply(plan, f2(), f2(dt=torch.float32)),
+        lambda: pmgw.pmg_vcycle(plan, f2(n2 // 2), f2()),
+        lambda: pmgw.adjoint_solve(plan, f2(), f2(n2 + 1)),
+        lambda: plan.set_geometry(f1(), f1(n1 - 1), f1()),
+        lambda: pmgw.rk4_stage(plan, 1, 0.01, f1(), f2(), f2(), f1(n1 - 1), f2(), f2(), f1(), f2()),
+        lambda: pmgw.rk4_stage(plan, 1, 0.01, f1(), f2(), f2(n2 - 1), f1(), f2(), f2(), f1(), f2()),
+        lambda: pmgw.rk4_stage_adjoint(plan, 1, 0.01, f1(), {q: f2() for q in ("u", "w", "Ku", "Kw")}
+                                       | {"eta": f1(), "Keta": f1()},
+                                       {q: f2() for q in ("u", "w", "Ku", "Kw")}
+                                       | {"eta": f1(), "Keta": f1()}, f1(),
+                                       info_dev=f1(2 * plan.ntanks)),
+    ]
+    for i, call in enumerate(calls):
+        with pytest.raises(pmgw.PmgwError) as ei:
+            call()
+        assert ei.value.code == pmgw.EINVAL, i
+        assert "elements" in str(ei.value) or "float64" in str(ei.value), (i, str(ei.value))

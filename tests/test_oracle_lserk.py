@@ -103,3 +103,79 @@ def test_time_convergence_fourth_order():
     e1 = np.abs(e[0].eta - ref.eta).max()
     e2 = np.abs(e[1].eta - ref.eta).max()
     assert e1 / e2 > 10.0
+
+
+# --------------------------------------------------------------------------- forcing pin
+#
+# The forcing of a stage is the rate of change of the velocity at fixed sigma (Sec. 2.1, the
+# sigma-transformed momentum equations). For velocity fields u(x, z), w(x, z) given in closed form
+# and the nodes z = sigma d(x) - h(x) of a sloped bed under a moving surface with rate eta_t, the
+# chain rule gives that rate as the physical-space acceleration plus the motion of the nodes:
+#   F_u = -(u u_x + w u_z) - g eta_x + nu (u_xx + u_zz) + sigma eta_t u_z,
+#   F_w = -(u w_x + w w_z)           + nu (w_xx + w_zz) + sigma eta_t w_z,
+# (z = sigma d - h moves at dz/dt = sigma eta_t at fixed sigma). Every term is evaluated from the
+# closed forms below, with no spectral derivative, so the pin fixes the advection velocity
+# w_sigma = sigma_t + u sigma_x + w / d with sigma_t = -sigma eta_t / d, the sign of every term and
+# the viscous operator, at amplitudes where the nonlinear terms are of order one.
+
+def _forcing_fields(x, z):
+    """u, w and their first and second derivatives (closed form) at physical points (x, z)."""
+    a, b, c = 0.6, 0.4, 0.3
+    ez = np.exp(0.5 * z)
+    u = a * np.cos(x) * ez + c * np.sin(2 * x) * z ** 2
+    ux = -a * np.sin(x) * ez + 2 * c * np.cos(2 * x) * z ** 2
+    uz = 0.5 * a * np.cos(x) * ez + 2 * c * np.sin(2 * x) * z
+    uxx = -a * np.cos(x) * ez - 4 * c * np.sin(2 * x) * z ** 2
+    uzz = 0.25 * a * np.cos(x) * ez + 2 * c * np.sin(2 * x)
+    w = b * np.sin(x) * np.cosh(z) + c * np.cos(3 * x) * z
+    wx = b * np.cos(x) * np.cosh(z) - 3 * c * np.sin(3 * x) * z
+    wz = b * np.sin(x) * np.sinh(z) + c * np.cos(3 * x)
+    wxx = -b * np.sin(x) * np.cosh(z) - 9 * c * np.cos(3 * x) * z
+    wzz = b * np.sin(x) * np.cosh(z)
+    return (u, ux, uz, uxx, uzz), (w, wx, wz, wxx, wzz)
+
+
+def _forcing_case(nx=64, nz=17, nu=0.05):
+    L = 2 * math.pi
+    x = sp.x_nodes(nx, L)
+    h = 1.0 + 0.15 * np.sin(x)
+    eta = 0.08 * np.cos(x) + 0.03 * np.sin(2 * x)
+    eta_x = -0.08 * np.sin(x) + 0.06 * np.cos(2 * x)
+    eta_t = 0.2 * np.sin(x) - 0.1 * np.cos(3 * x)
+    sig = sp.cgl_sigma(nz - 1)
+    d = h + eta
+    X = np.broadcast_to(x, (nz, nx))
+    Z = sig[:, None] * d[None, :] - h[None, :]
+    (u, ux, uz, uxx, uzz), (w, wx, wz, wxx, wzz) = _forcing_fields(X, Z)
+    ph = lserk.Physics(nu=nu)
+    S = sig[:, None] * eta_t[None, :]
+    want_u = -(u * ux + w * uz) - ph.g * eta_x[None, :] + nu * (uxx + uzz) + S * uz
+    want_w = -(u * wx + w * wz) + nu * (wxx + wzz) + S * wz
+    g = op.Geometry(h, eta, L)
+    return u, w, eta, eta_t, g, ph, want_u, want_w
+
+
+def test_forcing_matches_closed_form_on_sloped_moving_geometry():
+    u, w, eta, eta_t, g, ph, want_u, want_w = _forcing_case()
+    Fu, Fw = lserk.forcing(u, w, eta, eta_t, g, ph)
+    eu = np.abs(Fu - want_u).max() / np.abs(want_u).max()
+    ew = np.abs(Fw - want_w).max() / np.abs(want_w).max()
+    assert eu <= 1e-10 and ew <= 1e-10, (eu, ew)
+
+
+def test_forcing_pin_sees_each_term():
+    """Each term of the forcing changes the result far beyond the pin's tolerance on this case:
+    the node motion sigma eta_t u_z, the horizontal advection u u_x, the metric part u sigma_x of
+    the advection velocity and the viscous term."""
+    u, w, eta, eta_t, g, ph, want_u, want_w = _forcing_case()
+    sig = sp.cgl_sigma(u.shape[0] - 1)
+    uz = (sp.dsig_matrix(u.shape[0] - 1) @ u) * g.inv_d[None, :]
+    terms = {
+        "node motion": sig[:, None] * eta_t[None, :] * uz,
+        "u u_x": u * sp.dx(u, g.L),
+        "u sigma_x": u * g.sigma_x(sig) * (sp.dsig_matrix(u.shape[0] - 1) @ u),
+        "viscous": ph.nu * op.div(*op.grad(u, g, u.shape[0] - 1), g, u.shape[0] - 1),
+    }
+    scale = np.abs(want_u).max()
+    for name, t in terms.items():
+        assert np.abs(t).max() / scale > 1e-3, name
