@@ -214,6 +214,27 @@ int rk4_stage_adjoint(pmgw_plan plan, int32_t k, double dt, const double* h, con
                       double* Kwb, double* Ketab, double* hbar, double rtol, int32_t maxit,
                       pmgw_info* info_dev);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pmgw_set_geometry followed by poisson_solve, run in
+ * the library's static scratch array instead of a bound workspace. The plan needs no workspace
+ * (one bound to it is neither used nor changed) and must have been created on the current
+ * device. The array holds 48 MiB per device (every single tank up to 1024 x 33 in either
+ * precision fits); a plan whose pmgw_workspace_bytes exceeds it is refused with
+ * PMGW_EWORKSPACE before anything is launched. The call allocates nothing: the array is a
+ * file-scope device array, present on each device the library runs on until the process ends.
+ * Each device has one such array, shared by every call on that device, and it keeps the last
+ * call's contents: the first call of a plan (and the first after another plan used the array)
+ * copies the plan's constant tables into it from host memory, later calls of the same plan only
+ * launch kernels (every other value the call reads, it first writes). Calls that overlap on one
+ * device -- on different streams, plans or threads -- race on the array and must not be made.
+ * The Nz classes of a batch run one after another on the plan's stream. Arguments, outputs,
+ * info and return values as for pmgw_set_geometry and poisson_solve.
+ */
+int poisson_solve_noalloc(pmgw_plan plan, const double* h, const double* eta_old,
+                          const double* eta_new, const double* b, double* p, double rtol,
+                          int32_t maxit, pmgw_info* info_host, pmgw_info* info_dev);
+
 /* Release the plan (not the workspace, which the caller owns). NULL is ignored. */
 void pmgw_plan_destroy(pmgw_plan plan);
 

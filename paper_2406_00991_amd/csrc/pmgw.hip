@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "../../include/pmgw.h"
@@ -20,6 +22,8 @@ static_assert(sizeof(pmgw_info) == sizeof(pmgw_info_dev), "info layout");
 namespace {
 
 thread_local std::string g_err;
+
+std::atomic<uint64_t> g_plan_gen{0};   // owner tags of the static scratch array
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -184,6 +188,8 @@ struct pmgw_plan_s {
   int64_t total = 0;
   char* ws = nullptr;
   bool geometry_set = false;
+  bool serial = false;     // run the Nz classes one after another on `stream` (no side streams)
+  uint64_t gen = 0;        // unique id of the plan (owner tag of the static scratch array)
   int threads = 256;
   // launch timing of the solve kernels (pmgw_profile): one event pair per solve call
   std::vector<hipEvent_t> ev0, ev1;
@@ -292,7 +298,7 @@ int ensure_side_streams(pmgw_plan p) {
 template <typename TV, bool TR>
 int launch_all(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
                pmgw_info_dev* info, const KOpts& o) {
-  const bool multi = p->nclasses > 1;
+  const bool multi = p->nclasses > 1 && !p->serial;
   if (multi) {
     int rc = ensure_side_streams(p);
     if (rc) return rc;
@@ -423,6 +429,7 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   p->stream = reinterpret_cast<hipStream_t>(stream);
   if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
   p->threads = o.threads;
+  p->gen = g_plan_gen.fetch_add(1) + 1;
   const int vb = precision == PMGW_FP64 ? 8 : 4;   // V-cycle word size
   const int m = o.restart;
 
@@ -976,4 +983,85 @@ extern "C" int rk4_stage_adjoint(pmgw_plan p, int32_t k, double dt, const double
     if (rc) return rc;
   }
   return PMGW_OK;
+}
+
+// ----------------------------------------------------------------------------- static scratch
+//
+// For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+// harnesses that forbid hipMalloc): poisson_solve_noalloc runs the geometry and the solve in this
+// file-scope device array instead of a caller-bound workspace. Each GPU that the library runs on
+// holds its own copy until the process ends. In host code the name `scratch` is only a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per device, and is kept in
+// g_scratch below.
+
+constexpr size_t kScratchBytes = size_t(48) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};          // device address of `scratch` on each device
+uint64_t g_scratch_owner[kMaxDevices] = {}; // gen of the plan whose constant tables it holds
+
+// Device address of the scratch array on device dev (the current device), looked up on the first
+// call for that device.
+int scratch_for_device(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(PMGW_EDEVICE, "device index out of range");
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0)
+      return fail(PMGW_EDEVICE, "static scratch array is not 256-byte aligned");
+    g_scratch[dev] = reinterpret_cast<char*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return PMGW_OK;
+}
+
+}  // namespace
+
+extern "C" int poisson_solve_noalloc(pmgw_plan p, const double* h, const double* eta_old,
+                                     const double* eta_new, const double* b, double* x,
+                                     double rtol, int32_t maxit, pmgw_info* info_host,
+                                     pmgw_info* info_dev) {
+  g_err.clear();
+  if (!p) return fail(PMGW_EINVAL, "plan is NULL");
+  if (!h || !eta_old || !eta_new || !b || !x)
+    return fail(PMGW_EINVAL, "h, eta_old, eta_new, b and p must be non-NULL");
+  if (b == x) return fail(PMGW_EINVAL, "b and p must not overlap");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PMGW_EINVAL, "rtol must be positive");
+  if (maxit < 1) return fail(PMGW_EINVAL, "maxit must be >= 1");
+  if ((size_t)p->total > kScratchBytes)
+    return fail(PMGW_EWORKSPACE, "plan needs " + std::to_string(p->total) +
+                                     " bytes of workspace; the static scratch array holds " +
+                                     std::to_string(kScratchBytes));
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != p->device) return fail(PMGW_EINVAL, "the plan's device is not the current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  char* ws = nullptr;
+  int rc = scratch_for_device(dev, &ws);
+  if (rc) return rc;
+  // the array keeps the last call's contents: copy this plan's constant tables in unless they
+  // are still there (every other byte the call reads it first writes)
+  if (g_scratch_owner[dev] != p->gen) {
+    e = hipMemcpyAsync(ws, p->image.data(), p->image.size(), hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy of constant tables into the static scratch");
+    g_scratch_owner[dev] = p->gen;
+  }
+  char* const saved_ws = p->ws;
+  const bool saved_geo = p->geometry_set, saved_serial = p->serial;
+  p->ws = ws;
+  p->serial = true;   // no side streams: they would be created on first use
+  rc = pmgw_set_geometry(p, h, eta_old, eta_new);
+  if (rc == PMGW_OK) rc = solve_entry(p, false, b, x, rtol, maxit, info_host, info_dev);
+  const std::string msg = g_err;
+  p->ws = saved_ws;
+  p->geometry_set = saved_geo;
+  p->serial = saved_serial;
+  g_err = msg;
+  return rc;
 }

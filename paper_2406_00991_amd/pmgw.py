@@ -81,6 +81,8 @@ def lib():
         L.pmgw_plan_destroy.argtypes = [_vp]
         L.pmgw_plan_destroy.restype = None
         L.pmgw_last_error.restype = ctypes.c_char_p
+        L.poisson_solve_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double,
+                                            ctypes.c_int32, ctypes.POINTER(Info), _vp]
         L.pmgw_profile.argtypes = [_vp, ctypes.c_int32]
         L.pmgw_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), _dp, _dp]
         _lib = L
@@ -310,6 +312,28 @@ def _solve(name, plan, b, p, rtol, maxit, sync, info_dev):
     out = [(i.iters, i.status, i.relres) for i in infos]
     if rc == NOCONV:
         warnings.warn(name + ": a tank did not converge: " +
+                      lib().pmgw_last_error().decode())
+    return out
+
+
+def poisson_solve_noalloc(plan, h, eta_old, eta_new, b, p, rtol=1e-10, maxit=100, sync=True,
+                          info_dev=None):
+    """Geometry and solve in the library's static scratch array (no workspace, no device
+    allocation). Returns per-tank info like poisson_solve."""
+    *geo, bp, pp, dptr = _fields(plan, (h, 1), (eta_old, 1), (eta_new, 1), (b, 2), (p, 2),
+                                 (info_dev, "i1"))
+    infos = (Info * plan.ntanks)() if sync else None
+    rc = lib().poisson_solve_noalloc(plan._h, *geo, bp, pp, float(rtol), int(maxit), infos, dptr)
+    _trace("poisson_solve_noalloc")
+    if rc < 0:
+        err = PmgwError(rc, lib().pmgw_last_error().decode())
+        err.info = [(i.iters, i.status, i.relres) for i in infos] if infos is not None else None
+        raise err
+    if not sync:
+        return None
+    out = [(i.iters, i.status, i.relres) for i in infos]
+    if rc == NOCONV:
+        warnings.warn("poisson_solve_noalloc: a tank did not converge: " +
                       lib().pmgw_last_error().decode())
     return out
 

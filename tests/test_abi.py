@@ -112,3 +112,19 @@ def test_binding_rejects_short_and_mistyped_tensors():
             call()
         assert ei.value.code == pmgw.EINVAL, i
         assert "elements" in str(ei.value) or "float64" in str(ei.value), (i, str(ei.value))
+
+
+def test_noalloc_refuses_oversize_plan_before_touching_the_device():
+    """poisson_solve_noalloc checks the plan's workspace size against its static array (48 MiB)
+    before any HIP call, so this runs without a GPU."""
+    rc, h = _create([1024, 1024], [33, 33], [10.0, 10.0])
+    assert rc == 0
+    L = pmgw.lib()
+    assert L.pmgw_workspace_bytes(h) > 48 << 20
+    x = ctypes.c_void_p(0x1000)
+    y = ctypes.c_void_p(0x2000)
+    assert L.poisson_solve_noalloc(h, x, x, x, x, y, 1e-10, 10, None, None) == pmgw.EWORKSPACE
+    assert b"static scratch" in L.pmgw_last_error()
+    assert L.poisson_solve_noalloc(h, x, x, x, x, x, 1e-10, 10, None, None) == pmgw.EINVAL
+    assert L.poisson_solve_noalloc(None, x, x, x, x, y, 1e-10, 10, None, None) == pmgw.EINVAL
+    L.pmgw_plan_destroy(h)
