@@ -206,18 +206,65 @@ def run_batch(seed, ntanks, reps, rtol, threads=0):
                          "alg_bytes_per_batch": byts}}
 
 
+# ----------------------------------------------------------------------------- bar workload
+def run_bar(seeds, reps, rtol):
+    """The 1024 x 33 trapezoidal bar, first-stage problem from rest, one tank per seed, in the
+    mixed and the float64 plan: mean launch time of one solve from zero (HIP events on the plan's
+    stream, `reps` solves per seed after one warm-up), solves/s = 1 / that time, iterations, and
+    the solve kernel's algorithmic bytes over its launch time against the HBM peak."""
+    import torch
+
+    from paper_2406_00991_amd import pmgw
+    from paper_2406_00991_amd import workloads as wl
+    out = {"workload": f"trapezoidal bar, Nx=1024 x Nz=33, depth 0.4 to 0.1 (slopes 1:20, 1:10), "
+                       f"seeded monochromatic wave plus 1% noise, first-stage problem from rest, "
+                       f"seeds {seeds[0]}..{seeds[-1]}, one tank per solve, rtol {rtol:g}"}
+    for precision, ws in (("mixed", 4), ("fp64", 8)):
+        ms, its, byts = [], [], []
+        for seed in seeds:
+            pr = wl.bar(seed, 1024, 33)
+            plan = pmgw.Plan([1024], [33], [pr["L"]], precision=precision)
+            dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64,
+                                         device="cuda")
+            plan.set_geometry(dev(pr["h"]), dev(pr["eta_old"]), dev(pr["eta_new"]))
+            b, p = dev(pr["b"]), plan.field()
+            info = pmgw.poisson_solve(plan, b, p, rtol=rtol, maxit=300)
+            pmgw.profile_start(plan, reps)
+            for _ in range(reps):
+                p.zero_()
+                pmgw.poisson_solve(plan, b, p, rtol=rtol, maxit=300, sync=False)
+            n, tot, _ = pmgw.profile_read(plan)
+            pmgw.profile_start(plan, 0)
+            ms.append(tot / max(n, 1))
+            its.append(info[0][0])
+            byts.append(solve_bytes(1024, 33, info[0][0], ws))
+        t = float(np.mean(ms)) * 1e-3
+        alg = float(np.mean(byts))
+        out[precision] = {"value": 1.0 / t, "unit": "solves/s", "mean_launch_ms": 1e3 * t,
+                          "launch_ms_per_seed": ms, "iters": its,
+                          "roofline": {"bound": "hbm", "achieved": alg / t / 1e9,
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": alg / t / 1e9 / HBM_PEAK_GBS,
+                                       "alg_bytes_per_launch": alg}}
+    out["mixed_speedup"] = out["fp64"]["mean_launch_ms"] / out["mixed"]["mean_launch_ms"]
+    return out
+
+
 # ----------------------------------------------------------------------------- oracle timing
-def cpu_baseline(wave, budget_s=15.0):
-    """The oracle as it stands: its RK stage with the p-multigrid FGMRES solve (warm-started,
-    1e-10), from the same initial state, for about budget_s seconds on the host's cores."""
+def _cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def _oracle_stages(wave, budget_s):
+    """The oracle's RK stages with its p-multigrid FGMRES solve (warm-started, 1e-10) from the
+    bench's initial state, for about budget_s seconds: (stages done, seconds)."""
     from oracle import krylov
     from oracle import lserk
     from oracle import operator as op
     from oracle import pmg
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count() or 1
 
     def solve(b, g_old, g_new, p0):
         H = pmg.Hierarchy(b.shape[1], b.shape[0] - 1, g_old, g_new, pmg.PmgOptions())
@@ -228,11 +275,56 @@ def cpu_baseline(wave, budget_s=15.0):
     while time.perf_counter() - t0 < budget_s:
         lserk.stage(n % 5 + 1, wave["dt"], wave["h"], wave["L"], s, solve)
         n += 1
-    el = time.perf_counter() - t0
+    return n, time.perf_counter() - t0
+
+
+def _dense_solve_s(nx, nz):
+    """Definition mode: seconds for one dense LU solve of the manufactured problem's operator
+    (assembly excluded), the median of 3 after one warm-up."""
+    from oracle import operator as op
+    from paper_2406_00991_amd import workloads as wl
+    import scipy.linalg as sla
+    pr = wl.manufactured(nx, nz)
+    g = op.Geometry(pr["h"], pr["eta_old"], pr["L"])
+    A = op.assemble(nx, nz - 1, g, g)
+    b = pr["b"].ravel()
+    ts = []
+    for _ in range(4):
+        t0 = time.perf_counter()
+        sla.lu_solve(sla.lu_factor(A), b)
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts[1:]))
+
+
+def cpu_baseline(wave, budget_s=12.0, budget_1t_s=6.0):
+    """The oracle as it stands, on the host's cores (BLAS threads pinned to the core count with
+    threadpoolctl; the FFTs are single-threaded): its RK stage with the p-multigrid FGMRES solve,
+    from the same initial state, for about budget_s seconds. Beside it: the same with one BLAS
+    thread, and the definition mode (dense LU) at 32 x 9 and 256 x 17."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = _cores()
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                       "")
+    except OSError:
+        pass
+    with threadpool_limits(limits=cores):
+        n, el = _oracle_stages(wave, budget_s)
+        lu_c1 = _dense_solve_s(32, 9)
+        lu_c2 = _dense_solve_s(256, 17)
+    with threadpool_limits(limits=1):
+        n1, el1 = _oracle_stages(wave, budget_1t_s)
+    blas = sorted({f"{d.get('internal_api')}" for d in threadpool_info()})
     return dict(value=n / el, unit="solves/s", cores=cores, kind="oracle",
                 sample=f"the first {n} RK stages (one pressure solve each) of the "
                        f"{wave['nx']}x{wave['nz']} Stokes-wave run, NumPy/SciPy float64, "
-                       f"{el:.1f} s")
+                       f"{el:.1f} s",
+                cpu=cpu, blas=blas,
+                one_thread={"value": n1 / el1, "unit": "solves/s",
+                            "sample": f"the first {n1} RK stages, {el1:.1f} s, 1 BLAS thread"},
+                dense_lu_s={"32x9": lu_c1, "256x17": lu_c2})
 
 
 def main():
@@ -244,6 +336,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-tank batched solve reported beside the headline")
+    ap.add_argument("--no-bar", action="store_true",
+                    help="skip the 1024 x 33 bar solves reported beside the headline")
     ap.add_argument("--calibrate-mib", type=int, default=0,
                     help="first run an elementwise negation of a float64 buffer of this size "
                          "(reads and writes it once), the known-traffic kernel that scales the "
@@ -328,6 +422,10 @@ def main():
     if not args.no_batch:
         out["batched"] = run_batch(0, 512, 5, rtol)
         print(f"# batch: {out['batched']['value']:.0f} tank-solves/s", file=sys.stderr, flush=True)
+    if not args.no_bar:
+        out["bar"] = run_bar([0, 1, 2, 3, 4], 5, rtol)
+        print(f"# bar: mixed {out['bar']['mixed']['value']:.0f} solves/s, fp64 "
+              f"{out['bar']['fp64']['value']:.0f} solves/s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wave)
     print(json.dumps(out))

@@ -69,7 +69,12 @@ typedef struct {
     int32_t threads;        /* threads per solve workgroup: 64, 128 or 256; 0 = 256 [0]      */
     int32_t adapt_omega_m;  /* 1: scale omega_m per tank by the depth-variation rule below [1]   */
     int32_t cycle;          /* FGMRES preconditioner: PMGW_CYCLE_V or PMGW_CYCLE_FMG [V]       */
-    int32_t reserved;       /* must be 0                                                       */
+    int32_t coarse_exact;   /* coarsest level (order 2): 0 = coarse_pairs smoothing pairs,
+                               1 = direct solve in float64 (paper Alg. 1), Nx <= 512 [0]    */
+    int32_t resident;       /* PMGW_MIXED V-cycles: 1 = keep the cycle's level fields in LDS
+                               for the tanks where they fit (Nz <= 17, 64 <= Nx <= 512, e.g.
+                               256 x 17 and 512 x 5), 0 = always in global memory. Same
+                               arithmetic either way [1]                                    */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */
@@ -84,6 +89,12 @@ typedef struct pmgw_plan_s* pmgw_plan;
 /* The depth-variation rule of adapt_omega_m: with c = 1/(d_old d_new) over the tank's columns
  * and r = max c / min c, omega_m is multiplied by min(1, 2 / (1 + (r/2)^0.4)); it is 1 for flat
  * and mildly varying depth (r <= 2) and about 0.56 at a depth ratio of 4.6. */
+
+/* The direct coarsest-level solve (coarse_exact = 1): pmgw_set_geometry forms, per tank, the
+ * order-2 operator with its Dirichlet surface row eliminated (2 Nx unknowns, every x column
+ * coupled through D_x) and inverts it on the device by Gauss-Jordan elimination with partial
+ * pivoting, in float64 (about 12 Nx^3 multiply-adds per tank and geometry, 96 Nx^2 bytes of
+ * workspace); each V-cycle then applies the stored inverse in float64, in mixed plans too. */
 
 /* Fill *opts with the defaults. */
 void pmgw_default_opts(pmgw_opts* opts);

@@ -20,9 +20,13 @@ Oracle (test infrastructure only).
 - Coarsest level (Alg. 1, p = 1): the paper uses a direct solver. Here the coarsest level still
   couples all Nx columns densely, so the oracle runs ``coarse_pairs`` smoothing pairs from a zero
   guess there (a fixed linear map); ``coarse='exact'`` uses a dense LU instead, for comparison.
-- V-cycle: zero initial guess; nu1 pre-smoothing pairs, residual, restriction, recursive call whose
-  result is the coarse correction (the listing leaves that assignment implicit), prolongation,
-  correction, nu2 post-smoothing pairs.
+- V-cycle (Alg. 1) as the correction scheme: on level l, smooth A_l x = f from the initial guess
+  (nu1 pairs), form the residual r = f - A_l x, restrict it, solve the coarse residual equation
+  A_{l+1} e = R r approximately by the same cycle from a zero guess, add the prolongated correction
+  P e, and smooth again (nu2 pairs). The value of the recursive call is the coarse correction e.
+- Full multigrid (Alg. 2) as nested iteration: the right-hand side is restricted to every level;
+  each level's V-cycle starts from the prolongated result of the next coarser level (from zero on
+  the coarsest level), ending with the finest level's V-cycle.
 """
 from dataclasses import dataclass, replace
 
@@ -178,7 +182,8 @@ class Hierarchy:
         self.P = [prolongation_matrix(m) for m in self.orders[:-1]]
 
     def vcycle(self, f, l=0, x0=None):
-        """Alg. 1 on level l from the initial guess x0 (zero when None)."""
+        """V-cycle (Alg. 1) for A_l x = f on level l from the initial guess x0 (zero when None):
+        the correction scheme described in the module docstring."""
         o = self.opts
         lev = self.levels[l]
         x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.result_type(f, x0))
@@ -198,10 +203,10 @@ class Hierarchy:
         return x
 
     def fmg(self, f):
-        """Alg. 2: from the coarsest level up, a V-cycle on each level started from the
-        prolongated result of the level below (zero on the coarsest level), the last one on the
-        finest level. The paper leaves the coarser right-hand sides implicit; here each is the
-        restriction R of the next finer one."""
+        """Full multigrid (Alg. 2) as nested iteration: right-hand sides f_l = R f_{l-1} on every
+        level (the paper does not say how the coarser right-hand sides are formed; restriction is
+        the reading taken), then from the coarsest level up a V-cycle for A_l u = f_l started from
+        the prolongated approximation of the level below (from zero on the coarsest level)."""
         fs = [np.asarray(f)]
         for l in range(len(self.levels) - 1):
             fs.append(self.R[l] @ fs[-1])

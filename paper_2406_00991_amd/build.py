@@ -30,7 +30,7 @@ FLAGS = [
 # (source, extra defines) of each translation unit
 UNITS = [
     ("pmgw.hip", []),
-    ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=0"]),
+    ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=0", "-DPMGW_TV_IS_FLOAT"]),
     ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=0"]),
     ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=1"]),
     ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=1"]),

@@ -197,15 +197,24 @@ struct pmgw_plan_s {
   bool prof_on = false;
   // side streams (default priority) and events that run the Nz classes of one solve call
   // concurrently, forked from and joined back to `stream`; created on first use
-  hipStream_t side[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t fork = nullptr, join[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // each class split for the mixed-precision V-cycle: rids = tanks whose cycle runs in LDS
+  // (pmgw_resident.hpp), xids = the others; rres = largest resident map (bytes) of the class
+  int64_t rids_off[5] = {0, 0, 0, 0, 0}, xids_off[5] = {0, 0, 0, 0, 0};
+  std::vector<int32_t> rids[5], xids[5];
+  int rmaxnx[5] = {0, 0, 0, 0, 0}, xmaxnx[5] = {0, 0, 0, 0, 0};
+  int64_t rres[5] = {0, 0, 0, 0, 0};
+  // launch groups 3 c + k of class c: k = 0 all tanks, 1 the resident part, 2 the rest; side
+  // streams (default priority) and events that run the groups of one solve call concurrently,
+  // forked from and joined back to `stream`; created on first use
+  hipStream_t side[15] = {};
+  hipEvent_t fork = nullptr, join[15] = {};
   int nclasses = 0;
   ~pmgw_plan_s() {
     for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev1) (void)hipEventDestroy(e);
-    for (int c = 0; c < 5; ++c) {
-      if (side[c]) (void)hipStreamDestroy(side[c]);
-      if (join[c]) (void)hipEventDestroy(join[c]);
+    for (int g = 0; g < 15; ++g) {
+      if (side[g]) (void)hipStreamDestroy(side[g]);
+      if (join[g]) (void)hipEventDestroy(join[g]);
     }
     if (fork) (void)hipEventDestroy(fork);
   }
@@ -237,6 +246,7 @@ KOpts kopts(const pmgw_plan_s* p) {
   o.omega_m = p->opts.omega_m;
   o.adapt = p->opts.adapt_omega_m;
   o.cycle = p->opts.cycle;
+  o.coarse_exact = p->opts.coarse_exact;
   return o;
 }
 
@@ -258,12 +268,33 @@ int solve_fftb(int threads, int maxnx) {
   return 32768;
 }
 
+// LDS bytes that the resident V-cycle of a tank needs beside the Krylov state: its map, the two
+// twiddle tables and the solve kernel's static LDS.
+int64_t resident_lds(int nz, int nx) {
+  return res_map_bytes(nz, nx) + 24LL * nx + (int64_t)sizeof(KrylovLds);
+}
+constexpr int64_t kLdsPerWorkgroup = 163840;
+
+struct GroupView {
+  int64_t off;
+  unsigned count;
+  int maxnx;
+};
+
+GroupView group_view(const pmgw_plan_s* p, int g) {
+  const int c = g / 3, k = g % 3;
+  if (k == 1) return {p->rids_off[c], (unsigned)p->rids[c].size(), p->rmaxnx[c]};
+  if (k == 2) return {p->xids_off[c], (unsigned)p->xids[c].size(), p->xmaxnx[c]};
+  return {p->ids_off[c], (unsigned)p->ids[c].size(), p->maxnx[c]};
+}
+
 template <typename TV, int NZ, bool TR>
-void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, double rtol,
+void launch_group(pmgw_plan p, int g, int mode, const double* in, double* out, double rtol,
                   int maxit, pmgw_info_dev* info, const KOpts& o, hipStream_t st) {
+  const GroupView v = group_view(p, g);
   SolveArgs a;
   a.descs = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
-  a.ids = reinterpret_cast<const int32_t*>(p->ws + p->ids_off[c]);
+  a.ids = reinterpret_cast<const int32_t*>(p->ws + v.off);
   a.ws = p->ws;
   a.mode = mode;
   a.in = in;
@@ -273,56 +304,77 @@ void launch_class(pmgw_plan p, int c, int mode, const double* in, double* out, d
   a.info = info;
   a.o = o;
   const int thr = p->opts.threads ? p->opts.threads : 256;
-  a.fftb = solve_fftb(thr, p->maxnx[c]);
-  launch_k_solve<TV, NZ, TR>((unsigned)p->ids[c].size(), thr, lds_bytes(a.fftb, p->maxnx[c]), st,
-                             a);
+  a.fftb = solve_fftb(thr, v.maxnx);
+  if constexpr (std::is_same<TV, float>::value && !TR && NZ <= kResMaxNz) {
+    if (g % 3 == 1) {
+      // the resident map lives in the first 2 fftb bytes, before the twiddles
+      const int64_t half = (p->rres[g / 3] + 511) / 512 * 256;
+      a.fftb = (int)std::max<int64_t>(a.fftb, half);
+      launch_k_solve_res<NZ>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
+      return;
+    }
+  }
+  launch_k_solve<TV, NZ, TR>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
 }
 
-// Creates the side streams and fork/join events once (only plans with several Nz classes).
+// Creates the side streams and fork/join events once (only plans with several launch groups).
 int ensure_side_streams(pmgw_plan p) {
   if (p->fork) return PMGW_OK;
   hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
-  for (int c = 0; c < 5 && e == hipSuccess; ++c) {
-    if (p->ids[c].empty()) continue;
-    e = hipStreamCreateWithFlags(&p->side[c], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[c], hipEventDisableTiming);
+  for (int g = 0; g < 15 && e == hipSuccess; ++g) {
+    if (group_view(p, g).count == 0) continue;
+    e = hipStreamCreateWithFlags(&p->side[g], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[g], hipEventDisableTiming);
   }
   if (e != hipSuccess) return hip_fail(e, "creating side streams");
   return PMGW_OK;
 }
 
-// One solve-kernel launch per Nz class. With several classes the launches go to side streams
-// that wait on an event recorded on the plan's stream and are joined back into it, so that the
-// classes run concurrently (a 512-tank batch has three classes); the order seen by later work on
-// the plan's stream is unchanged, and the fork/join pattern is valid under graph capture.
+// One solve-kernel launch per group of tanks: per Nz class, and for mixed-precision V-cycles per
+// part of a class (LDS-resident cycle or global-memory cycle). With several groups the launches go
+// to side streams that wait on an event recorded on the plan's stream and are joined back into
+// it, so that the groups run concurrently (a 512-tank batch has three classes); the order seen by
+// later work on the plan's stream is unchanged, and the fork/join pattern is valid under graph
+// capture.
 template <typename TV, bool TR>
 int launch_all(pmgw_plan p, int mode, const double* in, double* out, double rtol, int maxit,
                pmgw_info_dev* info, const KOpts& o) {
-  const bool multi = p->nclasses > 1 && !p->serial;
+  const bool split = std::is_same<TV, float>::value && !TR && o.cycle == PMGW_CYCLE_V &&
+                     (mode == MODE_SOLVE || mode == MODE_VCYCLE);
+  int gl[15], ng = 0;
+  for (int c = 0; c < 5; ++c) {
+    if (split && !p->rids[c].empty()) {
+      gl[ng++] = 3 * c + 1;
+      if (!p->xids[c].empty()) gl[ng++] = 3 * c + 2;
+    } else if (!p->ids[c].empty()) {
+      gl[ng++] = 3 * c;
+    }
+  }
+  const bool multi = ng > 1 && !p->serial;
   if (multi) {
     int rc = ensure_side_streams(p);
     if (rc) return rc;
     hipError_t e = hipEventRecord(p->fork, p->stream);
     if (e != hipSuccess) return hip_fail(e, "fork event");
   }
-  for (int c = 0; c < 5; ++c) {
-    if (p->ids[c].empty()) continue;
+  for (int q = 0; q < ng; ++q) {
+    const int g = gl[q];
     hipStream_t st = p->stream;
     if (multi) {
-      st = p->side[c];
+      st = p->side[g];
       hipError_t e = hipStreamWaitEvent(st, p->fork, 0);
       if (e != hipSuccess) return hip_fail(e, "side stream wait");
     }
-    switch (c) {
-      case 0: launch_class<TV, 3, TR>(p, 0, mode, in, out, rtol, maxit, info, o, st); break;
-      case 1: launch_class<TV, 5, TR>(p, 1, mode, in, out, rtol, maxit, info, o, st); break;
-      case 2: launch_class<TV, 9, TR>(p, 2, mode, in, out, rtol, maxit, info, o, st); break;
-      case 3: launch_class<TV, 17, TR>(p, 3, mode, in, out, rtol, maxit, info, o, st); break;
-      default: launch_class<TV, 33, TR>(p, 4, mode, in, out, rtol, maxit, info, o, st); break;
+    switch (g / 3) {
+      case 0: launch_group<TV, 3, TR>(p, g, mode, in, out, rtol, maxit, info, o, st); break;
+      case 1: launch_group<TV, 5, TR>(p, g, mode, in, out, rtol, maxit, info, o, st); break;
+      case 2: launch_group<TV, 9, TR>(p, g, mode, in, out, rtol, maxit, info, o, st); break;
+      case 3: launch_group<TV, 17, TR>(p, g, mode, in, out, rtol, maxit, info, o, st); break;
+      default: launch_group<TV, 33, TR>(p, g, mode, in, out, rtol, maxit, info, o, st); break;
     }
     if (multi) {
-      hipError_t e = hipEventRecord(p->join[c], st);
-      if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->join[c], 0);
+      hipError_t e = hipEventRecord(p->join[g], st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->join[g], 0);
       if (e != hipSuccess) return hip_fail(e, "join event");
     }
   }
@@ -378,6 +430,7 @@ void pmgw_default_opts(pmgw_opts* o) {
   o->threads = 0;
   o->adapt_omega_m = 1;
   o->cycle = PMGW_CYCLE_V;
+  o->resident = 1;
 }
 
 const char* pmgw_last_error(void) { return g_err.c_str(); }
@@ -411,6 +464,9 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     return fail(PMGW_EINVAL, "adapt_omega_m must be 0 or 1");
   if (o.cycle != PMGW_CYCLE_V && o.cycle != PMGW_CYCLE_FMG)
     return fail(PMGW_EINVAL, "cycle must be PMGW_CYCLE_V or PMGW_CYCLE_FMG");
+  if (o.coarse_exact != 0 && o.coarse_exact != 1)
+    return fail(PMGW_EINVAL, "coarse_exact must be 0 or 1");
+  if (o.resident != 0 && o.resident != 1) return fail(PMGW_EINVAL, "resident must be 0 or 1");
   for (int t = 0; t < ntanks; ++t) {
     const int n = nx[t], M = nz[t] - 1;
     if (n < 8 || n > 2048 || (n & (n - 1)) != 0)
@@ -418,6 +474,9 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     if (!valid_m(M))
       return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": Nz must be 3, 5, 9, 17 or 33");
     if (n < 2 * M) return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": Nx must be >= 2 (Nz - 1)");
+    if (o.coarse_exact && n > kCoarseExactMaxNx)
+      return fail(PMGW_EINVAL, "tank " + std::to_string(t) +
+                                   ": the direct coarsest solve needs Nx <= 512");
     if (!(L[t] > 0.0) || !std::isfinite(L[t]))
       return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": L must be positive and finite");
   }
@@ -461,6 +520,23 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     if (!p->ids[c].empty()) ++p->nclasses;
     p->ids_off[c] = cur;
     cur = align256(cur + 4 * (int64_t)p->ids[c].size());
+    for (int32_t t : p->ids[c]) {
+      const int tnz = nz[t], tnx = nx[t];
+      const bool res = precision == PMGW_MIXED && o.resident && tnz <= kResMaxNz && tnx >= 64 &&
+                       tnx <= 512 && resident_lds(tnz, tnx) <= kLdsPerWorkgroup;
+      if (res) {
+        p->rids[c].push_back(t);
+        p->rmaxnx[c] = std::max(p->rmaxnx[c], tnx);
+        p->rres[c] = std::max<int64_t>(p->rres[c], res_map_bytes(tnz, tnx));
+      } else {
+        p->xids[c].push_back(t);
+        p->xmaxnx[c] = std::max(p->xmaxnx[c], tnx);
+      }
+    }
+    p->rids_off[c] = cur;
+    cur = align256(cur + 4 * (int64_t)p->rids[c].size());
+    p->xids_off[c] = cur;
+    cur = align256(cur + 4 * (int64_t)p->xids[c].size());
   }
   p->tanks.resize(ntanks);
   p->off2d.assign(ntanks + 1, 0);
@@ -519,6 +595,10 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     d.a2 = cur; cur = align256(cur + 8LL * n);
     d.a3 = cur; cur = align256(cur + 8LL * n);
     d.aspec = cur; cur = align256(cur + 16LL * ((d.nz + 1) / 2) * d.nx);
+    if (o.coarse_exact) {
+      d.cw = cur; cur = align256(cur + 8LL * 6 * d.nx * d.nx);
+      d.cwt = cur; cur = align256(cur + 8LL * 6 * d.nx * d.nx);
+    }
     for (int l = 0; l < d.nlev; ++l) {
       LevelDesc& lv = d.lev[l];
       const int64_t nl = (int64_t)lv.nz * d.nx;
@@ -561,9 +641,14 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   p->image.assign(const_end, 0);
   std::memcpy(p->image.data() + p->desc_off, p->tanks.data(), sizeof(TankDesc) * ntanks);
   std::memcpy(p->image.data() + p->job_off, p->jobs.data(), sizeof(BlockJob) * p->jobs.size());
-  for (int c = 0; c < 5; ++c)
+  for (int c = 0; c < 5; ++c) {
     if (!p->ids[c].empty())
       std::memcpy(p->image.data() + p->ids_off[c], p->ids[c].data(), 4 * p->ids[c].size());
+    if (!p->rids[c].empty())
+      std::memcpy(p->image.data() + p->rids_off[c], p->rids[c].data(), 4 * p->rids[c].size());
+    if (!p->xids[c].empty())
+      std::memcpy(p->image.data() + p->xids_off[c], p->xids[c].data(), 4 * p->xids[c].size());
+  }
   for (int t = 0; t < ntanks; ++t) {
     const TankDesc& d = p->tanks[t];
     for (int l = 0; l < d.nlev; ++l) {
@@ -652,6 +737,12 @@ int pmgw_set_geometry(pmgw_plan p, const double* h, const double* eo, const doub
                        (int)p->jobs.size(), p->ws);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "block kernel launch");
+  if (p->opts.coarse_exact) {
+    hipLaunchKernelGGL(k_coarse_setup, dim3(p->ntanks), dim3(kCoarseThreads),
+                       lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream, d, p->ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "coarse set-up kernel launch");
+  }
   p->geometry_set = true;
   return PMGW_OK;
 }

@@ -234,13 +234,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The Stockham FFT of fft_lds for nr <= RM rows at a, a + N, ..., a + (nr-1) N of length N
-// (64 <= N <= 512), owned by one wavefront and done in place: each radix pass reads the inputs
-// of all rows before one wavefront sync and writes all outputs before the next, so the rows' LDS
-// and arithmetic latencies overlap; the twiddles of a butterfly are read once for all rows.
+// The Stockham FFT of fft_lds for nr <= RM rows at a, a + rs, ..., a + (nr-1) rs of length N
+// (64 <= N <= 512; row stride rs >= N, in complex elements), owned by one wavefront and done in
+// place: each radix pass reads the inputs of all rows before one wavefront sync and writes all
+// outputs before the next, so the rows' LDS and arithmetic latencies overlap; the twiddles of a
+// butterfly are read once for all rows.
 template <typename T, bool INV, int RM>
 __device__ void fft_wave_m(lptr<cpx<T>> a, int nr, int N, int log2N, lptr<const cpx<T>> tw,
-                           int lane) {
+                           int lane, int rs) {
   int p = 1;
   if (log2N & 1) {
     const int h = N >> 1;
@@ -248,7 +249,7 @@ __device__ void fft_wave_m(lptr<cpx<T>> a, int nr, int N, int log2N, lptr<const 
 #pragma unroll
     for (int q = 0; q < RM; ++q) {
       if (q < nr) {
-        const lptr<cpx<T>> s = a + q * N;
+        const lptr<cpx<T>> s = a + q * rs;
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
           const int i = lane + 64 * it;
@@ -260,7 +261,7 @@ __device__ void fft_wave_m(lptr<cpx<T>> a, int nr, int N, int log2N, lptr<const 
 #pragma unroll
     for (int q = 0; q < RM; ++q) {
       if (q < nr) {
-        const lptr<cpx<T>> d = a + q * N;
+        const lptr<cpx<T>> d = a + q * rs;
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
           const int i = lane + 64 * it;
@@ -281,7 +282,7 @@ __device__ void fft_wave_m(lptr<cpx<T>> a, int nr, int N, int log2N, lptr<const 
 #pragma unroll
     for (int q = 0; q < RM; ++q) {
       if (q < nr) {
-        const lptr<cpx<T>> s = a + q * N;
+        const lptr<cpx<T>> s = a + q * rs;
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
           const int i = lane + 64 * it;
@@ -318,7 +319,7 @@ __device__ void fft_wave_m(lptr<cpx<T>> a, int nr, int N, int log2N, lptr<const 
             const cpx<T> v0 = cadd(u0, u2), v1 = csub(u0, u2), v2 = cadd(u1, u3);
             const cpx<T> dd = csub(u1, u3);
             const cpx<T> v3 = INV ? cpx<T>{-dd.im, dd.re} : cpx<T>{dd.im, -dd.re};
-            const lptr<cpx<T>> d = a + q * N;
+            const lptr<cpx<T>> d = a + q * rs;
             lst<T>(d, j, cadd(v0, v2));
             lst<T>(d, j + p, cadd(v1, v3));
             lst<T>(d, j + 2 * p, csub(v0, v2));
@@ -493,11 +494,11 @@ __device__ void spectral_rows(int nrows, int N, int log2N, int fftb, LD ld, SM s
       const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
       wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
       wave_sync();
-      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane, N);
       for (int q = 0; q < nr; ++q)
         for (int n = lane; n < N; n += 64) A[q * N + n] = sm(n, A[q * N + n]);
       wave_sync();
-      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane, N);
       wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
       wave_sync();
     }
@@ -627,11 +628,11 @@ __device__ void dx2_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld, S
       wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
       for (int pass = 0; pass < 2; ++pass) {
         wave_sync();
-        fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+        fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane, N);
         for (int q = 0; q < nr; ++q)
           for (int n = lane; n < N; n += 64) A[q * N + n] = sm(n, A[q * N + n]);
         wave_sync();
-        fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+        fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane, N);
         if (pass == 0) wave_mid_pairs<T>(A, nr, N, lane, pp0, nw, nrows, stx, mid);
       }
       wave_store_pairs<T>(A, nr, N, lane, pp0, nw, nrows, sto);
@@ -656,7 +657,7 @@ __device__ void rows_fft_to_global(int nrows, int N, int log2N, int fftb, LD ld,
       const int nr = pp0 < npairs ? min(R, (npairs - pp0 + nw - 1) / nw) : 0;
       wave_load_pairs<T>(A, nr, N, lane, pp0, nw, nrows, ld);
       wave_sync();
-      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+      fft_wave_m<T, false, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane, N);
       for (int q = 0; q < nr; ++q)
         for (int n = lane; n < N; n += 64) gst<T>(spec, (pp0 + q * nw) * N + n, A[q * N + n]);
       wave_sync();
@@ -720,7 +721,7 @@ __device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
         }
       }
       wave_sync();
-      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane);
+      fft_wave_m<T, true, kWaveRows>(as_lds(A), nr, N, log2N, as_lds(tw), lane, N);
       if constexpr (std::is_same<ST, Axpy<T>>::value)
         wave_axpy_pairs<T>(A, nr, N, lane, pp0, nw, nrows, st);
       else
@@ -853,6 +854,7 @@ struct Ctx {
   int nx, log2nx, fftb;
   T kfac;
   Geo<T> g;
+  gptr<const double> cw, cwt;   // direct coarsest-level solve: W and W^T (null when not set up)
 };
 
 template <typename T>
@@ -861,6 +863,7 @@ __device__ __forceinline__ Ctx<T> uni(const Ctx<T>& c) {
   u.nx = uni(c.nx); u.log2nx = uni(c.log2nx); u.fftb = uni(c.fftb); u.kfac = uni(c.kfac);
   u.g.ao = uni(c.g.ao); u.g.bo = uni(c.g.bo); u.g.ido = uni(c.g.ido); u.g.an = uni(c.g.an);
   u.g.bn = uni(c.g.bn); u.g.idn = uni(c.g.idn); u.g.hx = uni(c.g.hx);
+  u.cw = uni(c.cw); u.cwt = uni(c.cwt);
   return u;
 }
 
@@ -1362,6 +1365,58 @@ __device__ __forceinline__ void fill_zero(P p, int n) {
   for (int e = tid(); e < n; e += nthr()) p[e] = 0;
 }
 
+// Direct solve of the coarsest level (order 2, three rows) from its stored inverse, in float64
+// whatever T: x_0 = f_0 and [x_1; x_2] = W [f_0; f_1; f_2], W = [Q | B^-1] (2 nx x 3 nx, see
+// k_coarse_setup), read through wt = W^T [3 nx][2 nx] so that the rows of W are read coalesced.
+// TR: the transpose of that linear map, x_0 = f_0 + Q^T [f_1; f_2], [x_1; x_2] = B^-T [f_1; f_2],
+// read through w = W [2 nx][3 nx]. f is staged as float64 in fin (LDS, 24 nx bytes; by default
+// the FFT buffer). f and x may be global or LDS fields.
+template <typename T, bool TR, class PF, class PX, class PS>
+__device__ void coarse_direct(int nx, gptr<const double> w, gptr<const double> wt, PF f, PX x,
+                              PS fin) {
+  const int n2 = 2 * nx, n3 = 3 * nx;
+  for (int e = tid(); e < n3; e += nthr()) fin[e] = (double)f[e];
+  __syncthreads();
+  constexpr int U = 8;   // loads in flight per thread (n3 and n2 are multiples of 8)
+  if constexpr (!TR) {
+    for (int r = tid(); r < n2; r += nthr()) {
+      double acc[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) acc[q] = 0.0;
+      for (int c = 0; c < n3; c += U) {
+        double a[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) a[q] = wt[(int64_t)(c + q) * n2 + r];
+#pragma unroll
+        for (int q = 0; q < U; ++q) acc[q] += a[q] * fin[c + q];
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < U; ++q) s += acc[q];
+      x[nx + r] = (T)s;
+    }
+    for (int i = tid(); i < nx; i += nthr()) x[i] = (T)fin[i];
+  } else {
+    for (int c = tid(); c < n3; c += nthr()) {
+      double acc[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) acc[q] = 0.0;
+      for (int r = 0; r < n2; r += U) {
+        double a[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) a[q] = w[(int64_t)(r + q) * n3 + c];
+#pragma unroll
+        for (int q = 0; q < U; ++q) acc[q] += a[q] * fin[nx + r + q];
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < U; ++q) s += acc[q];
+      x[c] = (T)((c < nx ? fin[c] : 0.0) + s);
+    }
+  }
+  __syncthreads();
+}
+
 // The V-cycle (paper Alg. 1) from a zero guess on the levels l, l+1, ..., whose row counts are
 // NZ, (NZ+1)/2, ..., 3 (the order halves per level). lev(l) returns the Lev of level l; input
 // lev(l).f, output lev(l).x.
@@ -1388,10 +1443,17 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   KOpts o;
   o.nu1 = uni(o_.nu1); o.nu2 = uni(o_.nu2); o.coarse_pairs = uni(o_.coarse_pairs);
   o.restart = uni(o_.restart); o.omega_c = uni(o_.omega_c); o.omega_m = uni(o_.omega_m);
-  o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle);
+  o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle); o.coarse_exact = uni(o_.coarse_exact);
   const int nx = c.nx;
   const T wc = T(o.omega_c), wm = T(o.omega_m);
   const Lev<T> L = uni(lev(l));
+  if constexpr (NZ == 3) {
+    if (uni(o_.coarse_exact) && c.cw) {
+      coarse_direct<T, TR>(nx, c.cw, c.cwt, gptr<const T>(L.f), L.x,
+                           as_lds(reinterpret_cast<double*>(g_fft_lds)));
+      return;
+    }
+  }
   enum { COL = 0, MODE = 1, DOWN = 2 };
   const int first = TR ? MODE : COL, second = TR ? COL : MODE;
   const int npre = (NZ == 3) ? o.coarse_pairs : (TR ? o.nu2 : o.nu1);
@@ -1469,7 +1531,7 @@ __device__ __noinline__ void fmg(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   KOpts o;
   o.nu1 = uni(o_.nu1); o.nu2 = uni(o_.nu2); o.coarse_pairs = uni(o_.coarse_pairs);
   o.restart = uni(o_.restart); o.omega_c = uni(o_.omega_c); o.omega_m = uni(o_.omega_m);
-  o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle);
+  o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle); o.coarse_exact = uni(o_.coarse_exact);
   if constexpr (NZ == 3) {
     vcycle<T, NZ, LP, false>(c, lev, l, o);
   } else {

@@ -2,6 +2,7 @@
 // flexible GMRES) and the workspace accessors it shares with the set-up and stage kernels.
 #pragma once
 #include "pmgw_device.hpp"
+#include "pmgw_resident.hpp"
 
 struct pmgw_info_dev {
   int32_t iters;
@@ -143,7 +144,9 @@ struct KrylovLds {
 // on A out = in with out as initial guess (paper Sec. 4.4): right preconditioning by one V-cycle,
 // modified Gram-Schmidt, Givens rotations, stop on the true relative residual.
 // TR = true does the same with A^T and the transposed cycle M^T (the adjoint solve).
-template <typename TV, int NZ, int MAXT, bool TR = false>
+// RES = true (float32 cycle, forward, V-cycle preconditioner, NZ <= 17) runs the cycle in LDS
+// (pmgw_resident.hpp); the launch's dynamic LDS then covers the resident map of every tank.
+template <typename TV, int NZ, int MAXT, bool TR = false, bool RES = false>
 __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ descs,
                                                 const int32_t* __restrict__ ids, char* ws,
                                                 int mode, const double* in, double* out,
@@ -167,6 +170,8 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
   Ctx<double> c64;
   c64.nx = nx; c64.log2nx = td.log2nx; c64.kfac = td.kfac; c64.fftb = fftb;
   c64.g = make_geo<double>(ws, td);
+  c64.cw = td.cw ? gcp<double>(ws, td.cw) : gptr<const double>(nullptr);
+  c64.cwt = td.cwt ? gcp<double>(ws, td.cwt) : gptr<const double>(nullptr);
   Lev<double> A64 = make_lev<double>(ws, td.lev[0]);
   A64.t1 = gmp<double>(ws, td.a1); A64.t2 = gmp<double>(ws, td.a2);
   A64.t3 = gmp<double>(ws, td.a3);
@@ -175,15 +180,43 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
   Ctx<TV> cv;
   cv.nx = nx; cv.log2nx = td.log2nx; cv.kfac = (TV)td.kfac; cv.fftb = fftb;
   cv.g = make_geo<TV>(ws, td);
+  cv.cw = c64.cw;
+  cv.cwt = c64.cwt;
   LevSet<TV> levs{ws, &td, gptr<TV>(nullptr), gptr<TV>(nullptr)};
   Lev<TV> L0 = levs(0);
+
+  // the resident cycle: src (float64, global) -> f_0 in LDS -> cycle -> x_0 -> dst (float64)
+  RCtx rc;
+  auto res_cycle = [&](const double* src, double* dst) {
+    if constexpr (RES) {
+      const RMap m0 = res_map<NZ, NZ>(nx);
+      res_load_geo<NZ>(ws, td);
+      ew_copy<float, double>(n, m0.f, src);
+      __syncthreads();
+      rvcycle<NZ, NZ>(rc);
+      ew_copy<double, float>(n, dst, m0.x);
+      __syncthreads();
+    }
+  };
+  if constexpr (RES) {
+    static_assert(std::is_same<TV, float>::value && !TR && NZ <= kResMaxNz, "resident cycle");
+    rc.nx = nx; rc.log2nx = td.log2nx; rc.fftb = fftb; rc.kfac = (float)td.kfac;
+    rc.wc = (float)o.omega_c; rc.wm = (float)o.omega_m;
+    rc.nu1 = o.nu1; rc.nu2 = o.nu2; rc.coarse_pairs = o.coarse_pairs;
+    rc.coarse_exact = o.coarse_exact; rc.td = &td; rc.ws = ws; rc.cw = cv.cw; rc.cwt = cv.cwt;
+  }
 
   if (mode == MODE_APPLY) {
     op_any<double, NZ, TR>(c64, A64, FIN_APPLY, as_global(b), as_global(x),
                          gptr<const double>(nullptr), gptr<double>(nullptr), 0.0);
     return;
   }
-  if (mode == MODE_VCYCLE || mode == MODE_FMG) {
+  if constexpr (RES) {
+    if (mode == MODE_VCYCLE) {
+      res_cycle(b, x);
+      return;
+    }
+  } else if (mode == MODE_VCYCLE || mode == MODE_FMG) {
     ew_copy<TV, double>(n, L0.f, b);
     __syncthreads();
     if constexpr (!TR) {
@@ -239,7 +272,9 @@ __global__ void __launch_bounds__(MAXT) k_solve(const TankDesc* __restrict__ des
       double* zj = Z + (int64_t)j * n;
       double* w = V + (int64_t)(j + 1) * n;
       // z_j = M^-1 v_j
-      if (std::is_same<TV, double>::value && !use_fmg) {
+      if constexpr (RES) {
+        res_cycle(vj, zj);
+      } else if (std::is_same<TV, double>::value && !use_fmg) {
         const LevSet<TV> lz{ws, &td, as_global(reinterpret_cast<TV*>(vj)),
                             as_global(reinterpret_cast<TV*>(zj))};
         vcycle<TV, NZ, LevSet<TV>, TR>(cv, lz, 0, o);

@@ -11,6 +11,7 @@ constexpr int kMaxLev = 5;          // orders 32, 16, 8, 4, 2
 constexpr int kMaxRestart = 32;     // FGMRES restart length bound (Hessenberg lives in LDS)
 constexpr int kFftBytes = 32768;    // one LDS ping-pong buffer of the row FFTs
 constexpr int kMaxNz = 33;
+constexpr int kCoarseExactMaxNx = 512;   // largest Nx of the direct coarsest-level solve
 
 enum : int32_t { PREC64 = 0, PREC32 = 1 };
 
@@ -43,6 +44,8 @@ struct TankDesc {
                                     // double mode-damping factor at +24
   int64_t V, Z;                     // FGMRES bases: (restart+1) x n and restart x n doubles
   int64_t a1, a2, a3, aspec;        // float64 operator temporaries (finest level)
+  int64_t cw, cwt;                  // direct solve of the coarsest level (0 unless enabled):
+                                    // W = [Q | B^-1] [2 nx][3 nx] and its transpose (float64)
   LevelDesc lev[kMaxLev];
 };
 
@@ -61,6 +64,7 @@ struct KOpts {
   double omega_c, omega_m;
   int32_t adapt;                    // scale omega_m by the tank's factor (scal + 24)
   int32_t cycle;                    // preconditioner: 0 V-cycle, 1 full multigrid
+  int32_t coarse_exact;             // coarsest level: 0 smoothing pairs, 1 direct solve
 };
 
 }  // namespace pmgw

@@ -66,6 +66,8 @@ __device__ __forceinline__ void rk_ctx(char* ws, const TankDesc& td, int fftb, C
   c.fftb = fftb;
   stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), td.nx, fftb);
   c.g = make_geo<double>(ws, td);
+  c.cw = gptr<const double>(nullptr);
+  c.cwt = gptr<const double>(nullptr);
   A = make_lev<double>(ws, td.lev[0]);
   A.t1 = gmp<double>(ws, td.a1);
   A.t2 = gmp<double>(ws, td.a2);

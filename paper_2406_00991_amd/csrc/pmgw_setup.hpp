@@ -220,3 +220,166 @@ __global__ void __launch_bounds__(64) k_blocks(const TankDesc* __restrict__ desc
 }
 
 }  // namespace pmgw
+
+namespace pmgw {
+
+// ----------------------------------------------------------------------------- coarsest level
+//
+// Direct solve of the coarsest level (paper Alg. 1: the order-2 problem is solved exactly).
+// The order-2 operator A_c (rows 0, 1, 2 = sigma 1, 1/2, 0, every row coupling all Nx columns
+// through D_x) has the identity as its Dirichlet row 0, so with y = [x_1; x_2] it reduces to
+// B y = [f_1; f_2] - C f_0, C = the coupling of rows 1, 2 to row 0. One workgroup per tank:
+//   1. c1 = D_x e_0 and c2 = D_x c1, the first columns of the circulant D_x and D_x^2 (by the
+//      same FFT derivative as the operator);
+//   2. W = [-C | B] ([2 nx][3 nx], float64) assembled entry by entry from the level's D_sigma,
+//      sigma nodes and the old/new metrics, with the operator's composite form: row 1 is
+//      Div^new Grad^old, row 2 the bed condition -(h_x G_x + G_z);
+//   3. Gauss-Jordan elimination with partial pivoting on the B columns, the -C columns carried
+//      along as extra right-hand sides: W becomes [Q | B^-1], Q = -B^-1 C;
+//   4. the transpose W^T, which the forward apply reads coalesced.
+// A zero or non-finite pivot marks the tank ENAN (its later solves report it).
+
+constexpr int kCoarseThreads = 1024;
+
+__global__ void __launch_bounds__(kCoarseThreads) k_coarse_setup(const TankDesc* __restrict__ descs,
+                                                                 char* ws) {
+  __shared__ double prow[3 * kCoarseExactMaxNx];
+  __shared__ double pcol[2 * kCoarseExactMaxNx];
+  __shared__ double c1[kCoarseExactMaxNx], c2[kCoarseExactMaxNx];
+  __shared__ int piv[2 * kCoarseExactMaxNx];
+  __shared__ double redv[kCoarseThreads / 64];
+  __shared__ int redi[kCoarseThreads / 64];
+  const TankDesc td = descs[blockIdx.x];
+  const int nx = td.nx;
+  if (!td.cw || !td.cwt || nx < 8 || nx > kCoarseExactMaxNx) return;
+  int32_t* status = reinterpret_cast<int32_t*>(mp<double>(ws, td.scal) + 2);
+  if (*status != ST_OK) return;
+  const int n2 = 2 * nx, n3 = 3 * nx;
+  const int lane = tid() & 63, wv = tid() >> 6, nw = nthr() >> 6;
+
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx,
+                 kGeoFftBytes);
+  double* c1p = c1;
+  double* c2p = c2;
+  dx_rows<double>(1, nx, td.log2nx, td.kfac, kGeoFftBytes,
+                  [=](int, int i) { return i == 0 ? 1.0 : 0.0; },
+                  [=](int, int i, double v) { c1p[i] = v; });
+  dx_rows<double>(1, nx, td.log2nx, td.kfac, kGeoFftBytes, [=](int, int i) { return c1p[i]; },
+                  [=](int, int i, double v) { c2p[i] = v; });
+
+  const LevelDesc& lc = td.lev[td.nlev - 1];
+  const double* Ds = cp<double>(ws, lc.ds[0]);
+  const double* sg = cp<double>(ws, lc.sig[0]);
+  const double* G = cp<double>(ws, td.geo64);
+  const double* ao = G + GEO_AO * nx;
+  const double* bo = G + GEO_BO * nx;
+  const double* ido = G + GEO_IDO * nx;
+  const double* an = G + GEO_AN * nx;
+  const double* bn = G + GEO_BN * nx;
+  const double* idn = G + GEO_IDN * nx;
+  const double* hx = G + GEO_HX * nx;
+  double* W = mp<double>(ws, td.cw);
+  double* WT = mp<double>(ws, td.cwt);
+  const int msk = nx - 1;
+
+  // entry of A_c at equation (j, i), unknown (m, k), j in {1, 2}
+  auto entry = [&](int j, int i, int m, int k) -> double {
+    const double dxik = c1p[(i - k) & msk];
+    double v = 0.0;
+    if (j == 1) {
+      if (m == 1) v += c2p[(i - k) & msk];
+      const double sxo1k = ao[k] + bo[k] * sg[1];
+      const double sxn1 = an[i] + bn[i] * sg[1];
+      v += dxik * Ds[3 + m] * (sxo1k + sxn1);
+      if (i == k) {
+        double s = 0.0, t = 0.0;
+        for (int l = 0; l < 3; ++l) {
+          s += Ds[3 + l] * (ao[i] + bo[i] * sg[l]) * Ds[3 * l + m];
+          t += Ds[3 + l] * Ds[3 * l + m];
+        }
+        v += sxn1 * s + idn[i] * ido[i] * t;
+      }
+    } else {
+      if (m == 2) v -= hx[i] * dxik;
+      if (i == k) v -= (hx[i] * (ao[i] + bo[i] * sg[2]) + ido[i]) * Ds[6 + m];
+    }
+    return v;
+  };
+  for (int r = wv; r < n2; r += nw) {
+    const int j = 1 + r / nx, i = r & msk;
+    for (int c = lane; c < n3; c += 64) {
+      const int m = c / nx, k = c & msk;
+      const double a = entry(j, i, m, k);
+      W[(int64_t)r * n3 + c] = (m == 0) ? -a : a;
+    }
+  }
+  __syncthreads();
+
+  bool bad = false;
+  for (int k = 0; k < n2; ++k) {
+    const int pc = nx + k;
+    // pivot row: largest |W[t][pc]| over t >= k, the smaller row on ties, NaN ranks highest
+    double best = -1.0;
+    int bi = n2;
+    for (int t = k + tid(); t < n2; t += nthr()) {
+      double v = fabs(W[(int64_t)t * n3 + pc]);
+      if (!(v >= 0.0)) v = INFINITY;
+      if (v > best) { best = v; bi = t; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
+    __syncthreads();
+    best = redv[0];
+    bi = redi[0];
+    for (int q = 1; q < nw; ++q)
+      if (redv[q] > best || (redv[q] == best && redi[q] < bi)) { best = redv[q]; bi = redi[q]; }
+    if (!(best > 0.0) || !isfinite(best) || bi >= n2) { bad = true; break; }
+    const int p = bi;
+    // swap rows p and k; the pivot row goes to LDS
+    for (int c = tid(); c < n3; c += nthr()) {
+      const double a = W[(int64_t)k * n3 + c], b = W[(int64_t)p * n3 + c];
+      if (p != k) W[(int64_t)p * n3 + c] = a;
+      prow[c] = b;
+    }
+    if (tid() == 0) piv[k] = p;
+    __syncthreads();
+    for (int t = tid(); t < n2; t += nthr()) pcol[t] = (t == k) ? 0.0 : W[(int64_t)t * n3 + pc];
+    __syncthreads();
+    const double inv = 1.0 / prow[pc];
+    for (int t = wv; t < n2; t += nw) {
+      double* row = W + (int64_t)t * n3;
+      if (t == k) {
+        for (int c = lane; c < n3; c += 64) row[c] = (c == pc) ? inv : prow[c] * inv;
+      } else {
+        const double fr = pcol[t] * inv;
+        for (int c = lane; c < n3; c += 64) row[c] = (c == pc) ? -fr : row[c] - fr * prow[c];
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid() == 0) *status = ST_ENAN;
+    return;
+  }
+  // undo the row pivoting on the columns of the inverse, last pivot first
+  for (int k = n2 - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k) {
+      for (int t = tid(); t < n2; t += nthr()) {
+        double* row = W + (int64_t)t * n3 + nx;
+        const double a = row[k];
+        row[k] = row[p];
+        row[p] = a;
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = wv; c < n3; c += nw)
+    for (int t = lane; t < n2; t += 64) WT[(int64_t)c * n2 + t] = W[(int64_t)t * n3 + c];
+}
+
+}  // namespace pmgw

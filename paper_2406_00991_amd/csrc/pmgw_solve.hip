@@ -33,4 +33,23 @@ template void launch_k_solve<PMGW_TV, 17, PMGW_TR != 0>(unsigned, int, size_t, h
 template void launch_k_solve<PMGW_TV, 33, PMGW_TR != 0>(unsigned, int, size_t, hipStream_t,
                                                          const SolveArgs&);
 
+#if PMGW_TR == 0
+template <int NZ>
+void launch_k_solve_res(unsigned grid, int threads, size_t lds, hipStream_t st,
+                        const SolveArgs& a) {
+  if constexpr (std::is_same<PMGW_TV, float>::value) {
+    hipLaunchKernelGGL((k_solve<float, NZ, kSolveMaxThreads, false, true>), dim3(grid),
+                       dim3(threads), lds, st, a.descs, a.ids, a.ws, a.mode, a.in, a.out, a.rtol,
+                       a.maxit, a.info, a.o, a.fftb);
+  }
+}
+#endif
+
+#if PMGW_TR == 0 && defined(PMGW_TV_IS_FLOAT)
+template void launch_k_solve_res<3>(unsigned, int, size_t, hipStream_t, const SolveArgs&);
+template void launch_k_solve_res<5>(unsigned, int, size_t, hipStream_t, const SolveArgs&);
+template void launch_k_solve_res<9>(unsigned, int, size_t, hipStream_t, const SolveArgs&);
+template void launch_k_solve_res<17>(unsigned, int, size_t, hipStream_t, const SolveArgs&);
+#endif
+
 }  // namespace pmgw

@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
                 ("filt_alpha", ctypes.c_double), ("filt_s", ctypes.c_double),
                 ("filt_fx", ctypes.c_double), ("filt_fz", ctypes.c_double),
                 ("threads", ctypes.c_int32), ("adapt_omega_m", ctypes.c_int32),
-                ("cycle", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cycle", ctypes.c_int32), ("coarse_exact", ctypes.c_int32),
+                ("resident", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

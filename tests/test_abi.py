@@ -47,7 +47,7 @@ def test_plan_rejects_bad_options_and_precision():
     rc, _ = _create([32], [9], [1.0], prec=7)
     assert rc == pmgw.EINVAL
     for bad in (dict(restart=0), dict(restart=33), dict(omega_c=0.0), dict(omega_m=2.0),
-                dict(nu1=-1), dict(threads=100), dict(threads=512)):
+                dict(nu1=-1), dict(threads=100), dict(threads=512), dict(coarse_exact=2)):
         rc, _ = _create([32], [9], [1.0], opts=pmgw.default_opts(**bad))
         assert rc == pmgw.EINVAL, bad
 
@@ -128,3 +128,17 @@ def test_noalloc_refuses_oversize_plan_before_touching_the_device():
     assert L.poisson_solve_noalloc(h, x, x, x, x, x, 1e-10, 10, None, None) == pmgw.EINVAL
     assert L.poisson_solve_noalloc(None, x, x, x, x, y, 1e-10, 10, None, None) == pmgw.EINVAL
     L.pmgw_plan_destroy(h)
+
+
+def test_coarse_exact_size_limit():
+    """The direct coarsest-level solve is offered up to Nx = 512 (its set-up grows like Nx^3)."""
+    o = pmgw.default_opts(coarse_exact=1)
+    rc, h = _create([512], [9], [1.0], opts=o)
+    assert rc == 0
+    small = pmgw.lib().pmgw_workspace_bytes(h)
+    pmgw.lib().pmgw_plan_destroy(h)
+    rc, h = _create([512], [9], [1.0])
+    assert small - pmgw.lib().pmgw_workspace_bytes(h) >= 2 * 8 * 6 * 512 * 512
+    pmgw.lib().pmgw_plan_destroy(h)
+    rc, h = _create([1024], [9], [1.0], opts=o)
+    assert rc == pmgw.EINVAL and b"512" in pmgw.lib().pmgw_last_error()

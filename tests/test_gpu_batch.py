@@ -1,12 +1,14 @@
 """The 512-tank batch of uneven (Nx, Nz) in one batched solve call (mixed precision), against the
 oracle.
 
-- Every tank: status OK, and the GPU solution's relative residual, evaluated with the ORACLE's
-  operator (the definition), is <= 1.5e-10 when the GPU solves to 1e-10 (the GPU's own stopping
-  test uses its own float64 operator, equal to the oracle's to ~1e-15).
-- Sampled tanks (one per (Nx, Nz) class present, up to 12): delta against the oracle's
-  p-multigrid FGMRES solution at 5e-12 (above the Nz = 33 rounding floors) is <= 1e-7 (residual
-  1e-10 times condition numbers of up to ~1e3 at these sizes).
+- Every tank, solved to 1e-10 (the benchmark's setting): status OK, and the GPU solution's
+  relative residual, evaluated with the ORACLE's operator (the definition), is <= 1.5e-10 (the
+  GPU's own stopping test uses its own float64 operator, equal to the oracle's to ~1e-15).
+- The same call refined to 1e-11 from that solution (float64 FGMRES around the float32 cycle):
+  sampled tanks (one per (Nx, Nz) class present, 12) are within 1e-10 of the oracle's
+  p-multigrid FGMRES solution at 2e-12. Measured on the oracle for these classes: a solution at
+  relres 1e-11 is within 1.1e-12 of one at 1e-13, and 1e-12 solutions within 2e-15; the dense LU,
+  whose own relres reaches 3.7e-11 at 512 x 17, is the less accurate of the two modes here.
 """
 import numpy as np
 import pytest
@@ -44,6 +46,9 @@ def test_batch_512_tanks_one_call():
         g = op.Geometry(t["h"], t["eta_old"], t["L"])
         worst = max(worst, op.relres(x, t["b"], g, g))
     assert worst <= 1.5e-10, worst
+    info = pmgw.poisson_solve(plan, b, p, rtol=1e-11, maxit=200)
+    assert all(i[1] == 0 for i in info), [i for i in info if i[1] != 0][:5]
+    sols = [a.cpu().numpy() for a in plan.split2d(p)]
     seen = {}
     for k, t in enumerate(tanks):
         seen.setdefault((t["nx"], t["nz"]), k)
@@ -51,10 +56,13 @@ def test_batch_512_tanks_one_call():
         t = tanks[k]
         g = op.Geometry(t["h"], t["eta_old"], t["L"])
         H = pmg.Hierarchy(t["nx"], t["nz"] - 1, g, g, pmg.PmgOptions())
-        ref, inf = krylov.fgmres(lambda v: op.apply(v, g, g), t["b"], H, rtol=5e-12, maxit=300)
-        assert inf["relres"] <= 2e-11, key     # Nz = 33 tanks have rounding floors near 1e-12
+        ref, inf = krylov.fgmres(lambda v: op.apply(v, g, g), t["b"], H, rtol=2e-12, restart=60,
+                                 maxit=120)
+        assert inf["relres"] <= 2e-12, key
         d = np.linalg.norm(sols[k] - ref) / np.linalg.norm(ref)
-        assert d <= 1e-7, (key, d)
+        print(f"batch tank {key}: GPU iters {info[k][0]}, relres {info[k][2]:.2e}, "
+              f"delta {d:.2e}", flush=True)
+        assert d <= 1e-10, (key, d)
 
 
 def test_batch_concurrent_classes_match_separate_plans():
