@@ -165,21 +165,28 @@ def run_precision(wave, precision, steps, warmup, rtol):
                 p=T.p.cpu().numpy())
 
 
-def run_batch(seed, ntanks, reps, rtol, threads=0):
+def run_batch(seed, ntanks, reps, rtol):
     """The batched workload: ntanks tanks of uneven (Nx, Nz), first-stage problems, one mixed
-    plan; `reps` timed batched solves (one poisson_solve call each, zero initial guess).
-    threads: workgroup size of the solve kernels (0 = the library default)."""
+    plan; `reps` timed batched solves (one poisson_solve call each, zero initial guess) in the
+    configuration the per-class tuner picks for this batch (searched here, on this device, on
+    these problems), with the library's default configuration timed beside it."""
     import torch
 
+    from paper_2406_00991_amd import autotune
     from paper_2406_00991_amd import pmgw
     from paper_2406_00991_amd import workloads as wl
     tanks = wl.batch(seed, ntanks)
-    plan = pmgw.Plan([t["nx"] for t in tanks], [t["nz"] for t in tanks], [t["L"] for t in tanks],
-                     precision="mixed", opts=pmgw.default_opts(threads=threads))
+    nx, nz, L = ([t[k] for t in tanks] for k in ("nx", "nz", "L"))
     cat = lambda key: torch.tensor(np.concatenate([np.asarray(t[key]).ravel() for t in tanks]),
                                    dtype=torch.float64, device="cuda")
-    plan.set_geometry(cat("h"), cat("eta_old"), cat("eta_new"))
-    b = cat("b")
+    h, eo, en, b = cat("h"), cat("eta_old"), cat("eta_new"), cat("b")
+    t_default = autotune.time_batch(nx, nz, L, h, eo, en, b, "mixed", pmgw.default_opts(),
+                                    rtol, reps)
+    t0 = time.perf_counter()
+    choice, log = autotune.tune(nx, nz, L, h, eo, en, b, "mixed", rtol, reps=2, cache=False)
+    t_search = time.perf_counter() - t0
+    plan = pmgw.Plan(nx, nz, L, precision="mixed", opts=pmgw.default_opts(**choice))
+    plan.set_geometry(h, eo, en)
     p = plan.field()
     pmgw.poisson_solve(plan, b, p, rtol=rtol, maxit=200, sync=False)
     torch.cuda.synchronize()
@@ -195,12 +202,20 @@ def run_batch(seed, ntanks, reps, rtol, threads=0):
     its = [i[0] for i in info]
     byts = sum(solve_bytes(t["nx"], t["nz"], k, 4) for t, k in zip(tanks, its))
     t_launch = tot_ms / max(launches, 1) * 1e-3
+    rows = pmgw.CLASS_ROWS
+    present = sorted({t["nz"] for t in tanks})
     return {"workload": f"{ntanks} tanks, seed {seed}, Nx in {{64,128,256,512}}, "
                         "Nz in {9,17,33}, first-stage problems, mixed precision, rtol 1e-10",
             "value": ntanks * reps / wall, "unit": "tank-solves/s",
             "mean_batch_ms": tot_ms / max(launches, 1), "points": int(sum(t["nx"] * t["nz"] for t in tanks)),
             "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
-            "status": sorted({i[1] for i in info}), "threads": threads,
+            "status": sorted({i[1] for i in info}),
+            "tuned": {"class_threads": {r: choice["class_threads"][rows.index(r)] for r in present},
+                      "class_resident": {r: ["default", "lds", "global"][
+                          choice["class_resident"][rows.index(r)]] for r in present},
+                      "default_config_batch_ms": t_default, "search_s": t_search,
+                      "search": [{"rows": r, "threads": t, "cycle": ["default", "lds", "global"][c],
+                                  "batch_ms": ms} for r, t, c, ms in log]},
             "roofline": {"bound": "hbm", "achieved": byts / t_launch / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": byts / t_launch / 1e9 / HBM_PEAK_GBS,
                          "alg_bytes_per_batch": byts}}

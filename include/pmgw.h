@@ -66,7 +66,9 @@ typedef struct {
     double filt_s;          /* filter order s [2]                                             */
     double filt_fx;         /* x cut-off fraction of Nx/2 [0.5]                               */
     double filt_fz;         /* sigma cut-off fraction of M [0.9]                              */
-    int32_t threads;        /* threads per solve workgroup: 64, 128 or 256; 0 = 256 [0]      */
+    int32_t threads;        /* threads per solve workgroup: 64, 128, 256 or 512; 0 = 256 [0]
+                               (512 applies to global-memory cycles of forward solves; LDS-
+                               resident cycles and adjoint solves use at most 256)           */
     int32_t adapt_omega_m;  /* 1: scale omega_m per tank by the depth-variation rule below [1]   */
     int32_t cycle;          /* FGMRES preconditioner: PMGW_CYCLE_V or PMGW_CYCLE_FMG [V]       */
     int32_t coarse_exact;   /* coarsest level (order 2): 0 = coarse_pairs smoothing pairs,
@@ -75,6 +77,11 @@ typedef struct {
                                for the tanks where they fit (Nz <= 17, 64 <= Nx <= 512, e.g.
                                256 x 17 and 512 x 5), 0 = always in global memory. Same
                                arithmetic either way [1]                                    */
+    int32_t class_threads[5];  /* per finest-level class (3, 5, 9, 17, 33 rows): threads per
+                               solve workgroup for that class's tanks, same values and limits
+                               as threads; 0 = use threads [0]                              */
+    int32_t class_resident[5]; /* per class: 0 = as resident, 1 = LDS-resident cycle where it
+                               fits, 2 = global-memory cycle [0]                            */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */

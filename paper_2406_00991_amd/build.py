@@ -34,6 +34,8 @@ UNITS = [
     ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=0"]),
     ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=1"]),
     ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=1"]),
+    ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=0", "-DPMGW_WIDE"]),
+    ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=0", "-DPMGW_WIDE"]),
     ("pmgw_stage.hip", ["-DPMGW_STAGE_PART=0"]),
     ("pmgw_stage.hip", ["-DPMGW_STAGE_PART=1"]),
 ]

@@ -303,18 +303,24 @@ void launch_group(pmgw_plan p, int g, int mode, const double* in, double* out, d
   a.maxit = maxit;
   a.info = info;
   a.o = o;
-  const int thr = p->opts.threads ? p->opts.threads : 256;
-  a.fftb = solve_fftb(thr, v.maxnx);
+  const int cls = p->opts.class_threads[g / 3];
+  int thr = cls ? cls : (p->opts.threads ? p->opts.threads : 256);
   if constexpr (std::is_same<TV, float>::value && !TR && NZ <= kResMaxNz) {
     if (g % 3 == 1) {
       // the resident map lives in the first 2 fftb bytes, before the twiddles
+      thr = std::min(thr, 256);
       const int64_t half = (p->rres[g / 3] + 511) / 512 * 256;
-      a.fftb = (int)std::max<int64_t>(a.fftb, half);
+      a.fftb = (int)std::max<int64_t>(solve_fftb(thr, v.maxnx), half);
       launch_k_solve_res<NZ>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
       return;
     }
   }
-  launch_k_solve<TV, NZ, TR>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
+  if constexpr (TR) thr = std::min(thr, 256);
+  a.fftb = solve_fftb(thr, v.maxnx);
+  if (!TR && thr > 256)
+    launch_k_solve_wide<TV, NZ>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
+  else
+    launch_k_solve<TV, NZ, TR>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
 }
 
 // Creates the side streams and fork/join events once (only plans with several launch groups).
@@ -341,11 +347,14 @@ int launch_all(pmgw_plan p, int mode, const double* in, double* out, double rtol
                pmgw_info_dev* info, const KOpts& o) {
   const bool split = std::is_same<TV, float>::value && !TR && o.cycle == PMGW_CYCLE_V &&
                      (mode == MODE_SOLVE || mode == MODE_VCYCLE);
+  // heaviest groups first (more rows, then the global-memory part of a class, whose tanks are
+  // the wider ones): the dispatcher places the workgroups of earlier launches first, so the
+  // longest solves of a batch start at once instead of waiting for CUs behind short ones
   int gl[15], ng = 0;
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 4; c >= 0; --c) {
     if (split && !p->rids[c].empty()) {
-      gl[ng++] = 3 * c + 1;
       if (!p->xids[c].empty()) gl[ng++] = 3 * c + 2;
+      gl[ng++] = 3 * c + 1;
     } else if (!p->ids[c].empty()) {
       gl[ng++] = 3 * c;
     }
@@ -458,8 +467,14 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     return fail(PMGW_EINVAL, "restart must be in [1, 32]");
   if (!(o.omega_c > 0.0 && o.omega_c < 2.0) || !(o.omega_m > 0.0 && o.omega_m < 2.0))
     return fail(PMGW_EINVAL, "damping factors must be in (0, 2)");
-  if (o.threads != 0 && o.threads != 64 && o.threads != 128 && o.threads != 256)
-    return fail(PMGW_EINVAL, "threads must be 0, 64, 128 or 256");
+  auto thr_ok = [](int t) { return t == 0 || t == 64 || t == 128 || t == 256 || t == 512; };
+  if (!thr_ok(o.threads)) return fail(PMGW_EINVAL, "threads must be 0, 64, 128, 256 or 512");
+  for (int c = 0; c < 5; ++c) {
+    if (!thr_ok(o.class_threads[c]))
+      return fail(PMGW_EINVAL, "class_threads must be 0, 64, 128, 256 or 512");
+    if (o.class_resident[c] < 0 || o.class_resident[c] > 2)
+      return fail(PMGW_EINVAL, "class_resident must be 0, 1 or 2");
+  }
   if (o.adapt_omega_m != 0 && o.adapt_omega_m != 1)
     return fail(PMGW_EINVAL, "adapt_omega_m must be 0 or 1");
   if (o.cycle != PMGW_CYCLE_V && o.cycle != PMGW_CYCLE_FMG)
@@ -522,7 +537,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     cur = align256(cur + 4 * (int64_t)p->ids[c].size());
     for (int32_t t : p->ids[c]) {
       const int tnz = nz[t], tnx = nx[t];
-      const bool res = precision == PMGW_MIXED && o.resident && tnz <= kResMaxNz && tnx >= 64 &&
+      const bool want = o.class_resident[c] == 0 ? o.resident != 0 : o.class_resident[c] == 1;
+      const bool res = precision == PMGW_MIXED && want && tnz <= kResMaxNz && tnx >= 64 &&
                        tnx <= 512 && resident_lds(tnz, tnx) <= kLdsPerWorkgroup;
       if (res) {
         p->rids[c].push_back(t);

@@ -28,6 +28,11 @@ struct SolveArgs {
 template <typename TV, int NZ, bool TR>
 void launch_k_solve(unsigned grid, int threads, size_t lds, hipStream_t st, const SolveArgs& a);
 
+// The forward kernel compiled for workgroups of up to 512 threads (two wavefronts per SIMD).
+template <typename TV, int NZ>
+void launch_k_solve_wide(unsigned grid, int threads, size_t lds, hipStream_t st,
+                         const SolveArgs& a);
+
 // The same kernel with the LDS-resident float32 V-cycle (forward, NZ <= 17).
 template <int NZ>
 void launch_k_solve_res(unsigned grid, int threads, size_t lds, hipStream_t st,

@@ -257,26 +257,52 @@ __device__ void r_colzero(int nx, const RLev& L, lptr<float> f, lptr<float> x, l
 //   X[M k1 + k2] = sum_l W_64^(l k1) [ W_N^(l k2) sum_r x[l + 64 r] W_M^(r k2) ],
 // so the forward transform is an M-point DFT in each lane's registers, a twiddle W_N^(l k2), and
 // for every k2 a 64-point radix-2 decimation-in-frequency transform across the lanes (the partner
-// of lane l at distance h is lane l ^ h, reached with ds_swizzle for h < 32 and ds_bpermute for
-// h = 32). The result is left in bit-reversed lane order: lane l', register k2 holds
+// of lane l at distance h is lane l ^ h, reached with DPP permutations for h < 16 and the
+// gfx950 lane swaps for h = 16, 32). The result is left in bit-reversed lane order: lane l', register k2 holds
 // X[M brev6(l') + k2]. The inverse runs the same steps backwards (decimation in time across the
 // lanes, conjugate twiddles, inverse register DFT) and takes that order to natural order, so a
 // multiplier in Fourier space needs no reordering at all. No LDS traffic and no wavefront sync.
 
 __device__ __forceinline__ int brev6(int l) { return (int)(__builtin_bitreverse32((unsigned)l) >> 26); }
 
-// The value of lane l ^ H.
+// The value of lane l ^ H for H < 16, by DPP lane permutations inside each row of 16 lanes
+// (plain VALU moves, no LDS round trip): quad_perm [1,0,3,2] (H = 1), quad_perm [2,3,0,1]
+// (H = 2), row_half_mirror then quad_perm [3,2,1,0] (l ^ 7 ^ 3 = l ^ 4) and row_ror:8 (H = 8).
 template <int H>
 __device__ __forceinline__ float lane_xor(float v) {
-  if constexpr (H == 32) {
-    return __shfl_xor(v, 32, 64);
+  const int x = __float_as_int(v);
+  if constexpr (H == 1) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false));
+  } else if constexpr (H == 2) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));
+  } else if constexpr (H == 4) {
+    const int m = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false));
   } else {
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (H << 10) | 0x1f));
+    static_assert(H == 8, "lane_xor covers distances below 16");
+    return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false));
   }
 }
 template <int H>
 __device__ __forceinline__ cpx<float> lane_xor(cpx<float> v) {
   return {lane_xor<H>(v.re), lane_xor<H>(v.im)};
+}
+
+// For H = 16 or 32: the gfx950 lane swap (v_permlane16_swap / v_permlane32_swap of a value with
+// itself) returns, on every lane, s0 = the value of the lower lane of the pair (l & ~H) and
+// s1 = that of the upper lane (l | H). The butterfly sum on the lower lane and difference on the
+// upper one are then both s0 + sg s1 (sg = +1 below, -1 above).
+template <int H>
+__device__ __forceinline__ float lane_pair_sum(float v, float sg) {
+  static_assert(H == 16 || H == 32, "lane_pair_sum covers distances 16 and 32");
+  const unsigned x = __float_as_uint(v);
+  if constexpr (H == 16) {
+    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return __uint_as_float(s[0]) + sg * __uint_as_float(s[1]);
+  } else {
+    const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return __uint_as_float(s[0]) + sg * __uint_as_float(s[1]);
+  }
 }
 
 // Per-lane twiddles for one row length: wl[k2] = W_N^(l k2) and, per cross-lane stage s
@@ -342,24 +368,23 @@ __device__ __forceinline__ void reg_dft(cpx<float> (&v)[M]) {
 // One cross-lane stage of the forward transform (distance H). With sg = +1 on the lower lane of
 // each pair and -1 on the upper one, and wl = 1 on the lower lane and W_(2h)^(l mod h) on the
 // upper one, the butterfly (x[j] + x[j+h], (x[j] - x[j+h]) W) is, on every lane,
-// v' = (p + sg v) wl with p the partner's value: no selects and no divergent branches. All
-// exchanges of the stage are issued before any result is used (one exchange latency per stage).
+// v' = (p + sg v) wl with p the partner's value: no selects and no divergent branches.
 template <int M, int R, int H>
 __device__ __forceinline__ void lane_dif(cpx<float> (&v)[R][M], cpx<float> w, int lane) {
   const bool up = (lane & H) != 0;
   const float sg = up ? -1.f : 1.f;
   const cpx<float> wl = up ? w : cpx<float>{1.f, 0.f};
-  cpx<float> p[R][M];
-#pragma unroll
-  for (int q = 0; q < R; ++q)
-#pragma unroll
-    for (int k2 = 0; k2 < M; ++k2) p[q][k2] = lane_xor<H>(v[q][k2]);
-  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int q = 0; q < R; ++q)
 #pragma unroll
     for (int k2 = 0; k2 < M; ++k2) {
-      const cpx<float> u = {p[q][k2].re + sg * v[q][k2].re, p[q][k2].im + sg * v[q][k2].im};
+      cpx<float> u;
+      if constexpr (H >= 16) {
+        u = {lane_pair_sum<H>(v[q][k2].re, sg), lane_pair_sum<H>(v[q][k2].im, sg)};
+      } else {
+        const cpx<float> p = lane_xor<H>(v[q][k2]);
+        u = {p.re + sg * v[q][k2].re, p.im + sg * v[q][k2].im};
+      }
       v[q][k2] = cmul(u, wl);
     }
 }
@@ -371,20 +396,18 @@ __device__ __forceinline__ void lane_dit(cpx<float> (&v)[R][M], cpx<float> w, in
   const bool up = (lane & H) != 0;
   const float sg = up ? -1.f : 1.f;
   const cpx<float> wl = up ? w : cpx<float>{1.f, 0.f};
-  cpx<float> p[R][M];
 #pragma unroll
   for (int q = 0; q < R; ++q)
 #pragma unroll
     for (int k2 = 0; k2 < M; ++k2) {
-      v[q][k2] = cmul(v[q][k2], wl);
-      p[q][k2] = lane_xor<H>(v[q][k2]);
+      const cpx<float> t = cmul(v[q][k2], wl);
+      if constexpr (H >= 16) {
+        v[q][k2] = {lane_pair_sum<H>(t.re, sg), lane_pair_sum<H>(t.im, sg)};
+      } else {
+        const cpx<float> p = lane_xor<H>(t);
+        v[q][k2] = {p.re + sg * t.re, p.im + sg * t.im};
+      }
     }
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int q = 0; q < R; ++q)
-#pragma unroll
-    for (int k2 = 0; k2 < M; ++k2)
-      v[q][k2] = {p[q][k2].re + sg * v[q][k2].re, p[q][k2].im + sg * v[q][k2].im};
 }
 
 // Forward transform of R rows (natural order in, bit-reversed lane order out).

@@ -35,7 +35,11 @@ class Opts(ctypes.Structure):
                 ("filt_fx", ctypes.c_double), ("filt_fz", ctypes.c_double),
                 ("threads", ctypes.c_int32), ("adapt_omega_m", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("coarse_exact", ctypes.c_int32),
-                ("resident", ctypes.c_int32)]
+                ("resident", ctypes.c_int32), ("class_threads", ctypes.c_int32 * 5),
+                ("class_resident", ctypes.c_int32 * 5)]
+
+# finest-level row counts of the per-class options (class_threads, class_resident)
+CLASS_ROWS = (3, 5, 9, 17, 33)
 
 
 class Info(ctypes.Structure):
@@ -113,7 +117,14 @@ def default_opts(**kw):
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
-        setattr(o, k, v)
+        if k in ("class_threads", "class_resident"):
+            # a list of 5 values, or a dict {rows: value} for some classes
+            arr = getattr(o, k)
+            items = v.items() if isinstance(v, dict) else zip(CLASS_ROWS, v)
+            for rows, val in items:
+                arr[CLASS_ROWS.index(int(rows))] = int(val)
+        else:
+            setattr(o, k, v)
     return o
 
 
