@@ -67,14 +67,16 @@ def traffic(fetch_dir, write_dir, copy_bytes, command, source_sha256, prefix="k_
                            "fetch_factor": ffac, "write_factor": wfac},
            "kernels": {}}
     for k, v in fetch.items():
-        m = re.search(r"pmgw::(\w+)<(float|double), (\d+)(?:, \d+, (true|false))?", k)
+        m = re.search(r"pmgw::(\w+)<(float|double), (\d+)(?:, \d+, (true|false)"
+                      r"(?:, (true|false))?)?", k)
         if not m or not m.group(1).startswith(prefix) or m.group(4) == "true":
             continue
         w = write.get(k, [0.0])
         fb = ffac * 1024.0 * sum(v) / len(v)
         wb = wfac * 1024.0 * sum(w) / len(w)
         prec = "mixed" if m.group(2) == "float" else "fp64"
-        key = f"{m.group(1)}<{m.group(2)},{m.group(3)}>/{prec}"
+        res = ",res" if m.group(5) == "true" else ""
+        key = f"{m.group(1)}<{m.group(2)},{m.group(3)}{res}>/{prec}"
         rec["kernels"][key] = {"dispatches": len(v), "fetch_bytes": fb, "write_bytes": wb,
                                "bytes_per_launch": fb + wb}
     return rec
