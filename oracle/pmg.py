@@ -17,6 +17,12 @@ Oracle (test infrastructure only).
   relaxation along x: the exact inverse of the x-averaged flat operator, mode by mode (damping
   omega_m, scaled per geometry by ``mode_damping``). One "pair" is a column step followed by a mode
   step, each from the current residual.
+- Optional third step of a pair (``bed_line``): the bed row's boundary condition couples the
+  columns through h_x D_x, which neither the column blocks (D_x has a zero diagonal) nor the
+  x-averaged mode blocks (h_x averages to zero) contain. The bed-line step solves the bed row's
+  own Nx x Nx block of A exactly, with the other rows held: x_M += L_b^-1 (f - A x)_M, where
+  L_b = -(diag(h_x) D_x + diag((h_x sigma_x[M] + 1/d) (D_sigma)_MM)) on the old geometry. It is
+  a line relaxation along x, the Sec. 4.3 smoother's block idea applied to the bed row.
 - Coarsest level (Alg. 1, p = 1): the paper uses a direct solver. Here the coarsest level still
   couples all Nx columns densely, so the oracle runs ``coarse_pairs`` smoothing pairs from a zero
   guess there (a fixed linear map); ``coarse='exact'`` uses a dense LU instead, for comparison.
@@ -47,6 +53,7 @@ class PmgOptions:
     coarse: str = "smooth"        # "smooth" (fixed pairs) or "exact" (dense LU)
     adapt_omega_m: bool = True    # scale omega_m by mode_damping(geometry)
     cycle: str = "V"              # preconditioner: "V" (Alg. 1) or "FMG" (Alg. 2)
+    bed_line: bool = False        # add the bed-line step to every smoothing pair
 
 
 def mode_damping(g_old, g_new):
@@ -156,9 +163,30 @@ class Level:
         r = f - self.apply(x)
         return x + omega * op.flat_mode_solve(r, self.mode)
 
+    def bed_block(self):
+        """L_b: the bed row's coupling to the bed-row unknowns (Nx x Nx), from the formula."""
+        g = self.g_old
+        M = self.M
+        dsmm = sp.dsig_matrix(M)[M, M]
+        sxm = g.sigma_x(sp.cgl_sigma(M))[M]
+        c = (g.hx * sxm + g.inv_d) * dsmm
+        return -(g.hx[:, None] * sp.dx_matrix(self.nx, g.L) + np.diag(c))
+
+    def bed_step(self, x, f):
+        """Exact line solve of the bed row: x_M += L_b^-1 (f - A x)_M."""
+        if getattr(self, "_bed_lu", None) is None:
+            self._bed_lu = sla.lu_factor(self.bed_block())
+        r = f - self.apply(x)
+        x = np.array(x, dtype=np.result_type(x, r))
+        x[self.M] = x[self.M] + sla.lu_solve(self._bed_lu, r[self.M])
+        return x
+
     def pair(self, x, f, o):
         x = self.column_step(x, f, o.omega_c)
-        return self.mode_step(x, f, o.omega_m)
+        x = self.mode_step(x, f, o.omega_m)
+        if o.bed_line:
+            x = self.bed_step(x, f)
+        return x
 
     def exact(self, f):
         if self._coarse_lu is None:
