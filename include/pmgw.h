@@ -82,6 +82,8 @@ typedef struct {
                                as threads; 0 = use threads [0]                              */
     int32_t class_resident[5]; /* per class: 0 = as resident, 1 = LDS-resident cycle where it
                                fits, 2 = global-memory cycle [0]                            */
+    int32_t bed_line;       /* 1 = end every smoothing pair with the bed-line step below
+                               (Nx <= 1024; the V-cycle then runs in global memory) [0]     */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */
@@ -96,6 +98,15 @@ typedef struct pmgw_plan_s* pmgw_plan;
 /* The depth-variation rule of adapt_omega_m: with c = 1/(d_old d_new) over the tank's columns
  * and r = max c / min c, omega_m is multiplied by min(1, 2 / (1 + (r/2)^0.4)); it is 1 for flat
  * and mildly varying depth (r <= 2) and about 0.56 at a depth ratio of 4.6. */
+
+/* The bed-line step (bed_line = 1), a line relaxation along x of the bed row (paper Sec. 4.3's
+ * block smoother idea applied to the bed condition): the bed row couples the columns through
+ * h_x D_x, which the column blocks and the x-averaged mode blocks leave out, and on steep,
+ * finely resolved beds (max|h_x| kappa_max / M^2 above ~0.3) the cycle without it amplifies
+ * the error. The step solves the bed row's own Nx x Nx block L_b of A exactly with the other
+ * rows held, x_M <- L_b^-1 (f_M + (h_x sigma_x[M] + 1/d) sum_{l<M} (D_sigma)_Ml x_l) on the old
+ * geometry. pmgw_set_geometry inverts L_b per level on the device (Gauss-Jordan with partial
+ * pivoting, float64, Nx^3 multiply-adds per level; 12 Nx^2 bytes of workspace per level). */
 
 /* The direct coarsest-level solve (coarse_exact = 1): pmgw_set_geometry forms, per tank, the
  * order-2 operator with its Dirichlet surface row eliminated (2 Nx unknowns, every x column

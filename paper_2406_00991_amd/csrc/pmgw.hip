@@ -247,6 +247,7 @@ KOpts kopts(const pmgw_plan_s* p) {
   o.adapt = p->opts.adapt_omega_m;
   o.cycle = p->opts.cycle;
   o.coarse_exact = p->opts.coarse_exact;
+  o.bed_line = p->opts.bed_line;
   return o;
 }
 
@@ -481,6 +482,7 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     return fail(PMGW_EINVAL, "cycle must be PMGW_CYCLE_V or PMGW_CYCLE_FMG");
   if (o.coarse_exact != 0 && o.coarse_exact != 1)
     return fail(PMGW_EINVAL, "coarse_exact must be 0 or 1");
+  if (o.bed_line != 0 && o.bed_line != 1) return fail(PMGW_EINVAL, "bed_line must be 0 or 1");
   if (o.resident != 0 && o.resident != 1) return fail(PMGW_EINVAL, "resident must be 0 or 1");
   for (int t = 0; t < ntanks; ++t) {
     const int n = nx[t], M = nz[t] - 1;
@@ -492,6 +494,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     if (o.coarse_exact && n > kCoarseExactMaxNx)
       return fail(PMGW_EINVAL, "tank " + std::to_string(t) +
                                    ": the direct coarsest solve needs Nx <= 512");
+    if (o.bed_line && n > kBedLineMaxNx)
+      return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": the bed-line step needs Nx <= 1024");
     if (!(L[t] > 0.0) || !std::isfinite(L[t]))
       return fail(PMGW_EINVAL, "tank " + std::to_string(t) + ": L must be positive and finite");
   }
@@ -538,7 +542,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
     for (int32_t t : p->ids[c]) {
       const int tnz = nz[t], tnx = nx[t];
       const bool want = o.class_resident[c] == 0 ? o.resident != 0 : o.class_resident[c] == 1;
-      const bool res = precision == PMGW_MIXED && want && tnz <= kResMaxNz && tnx >= 64 &&
+      const bool res = precision == PMGW_MIXED && want && !o.bed_line && tnz <= kResMaxNz &&
+                       tnx >= 64 &&
                        tnx <= 512 && resident_lds(tnz, tnx) <= kLdsPerWorkgroup;
       if (res) {
         p->rids[c].push_back(t);
@@ -628,6 +633,12 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
       lv.t2 = cur; cur = align256(cur + vb * nl);
       lv.t3 = cur; cur = align256(cur + vb * nl);
       lv.spec = cur; cur = align256(cur + 2LL * vb * ((lv.nz + 1) / 2) * d.nx);
+      if (o.bed_line) {
+        lv.bedinv = cur; cur = align256(cur + 8LL * d.nx * d.nx);
+        if (precision == PMGW_MIXED) {
+          lv.bedinv32 = cur; cur = align256(cur + 4LL * d.nx * d.nx);
+        }
+      }
     }
   }
   p->rk_off = cur;
@@ -753,6 +764,12 @@ int pmgw_set_geometry(pmgw_plan p, const double* h, const double* eo, const doub
                        (int)p->jobs.size(), p->ws);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "block kernel launch");
+  if (p->opts.bed_line) {
+    hipLaunchKernelGGL(k_bedline_setup, dim3(p->ntanks, kMaxLev), dim3(kBedLineThreads),
+                       lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream, d, p->ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "bed-line set-up kernel launch");
+  }
   if (p->opts.coarse_exact) {
     hipLaunchKernelGGL(k_coarse_setup, dim3(p->ntanks), dim3(kCoarseThreads),
                        lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream, d, p->ws);

@@ -847,6 +847,7 @@ struct Lev {
   gptr<const T> PT, RT;          // P^T [nzc][nz] and R^T [nz][nzc] (transposed V-cycle)
   gptr<T> x, f, r, t1, t2, t3, u;
   gptr<cpx<T>> spec;
+  gptr<const T> binv;            // bed-line inverse, transposed [nx][nx] (null when unused)
 };
 
 template <typename T>
@@ -874,7 +875,7 @@ __device__ __forceinline__ Lev<T> uni(const Lev<T>& L) {
   u.Ds = uni(L.Ds); u.sig = uni(L.sig); u.colinv = uni(L.colinv); u.modeinv = uni(L.modeinv);
   u.R = uni(L.R); u.P = uni(L.P); u.PT = uni(L.PT); u.RT = uni(L.RT);
   u.x = uni(L.x); u.f = uni(L.f); u.r = uni(L.r); u.t1 = uni(L.t1); u.t2 = uni(L.t2);
-  u.t3 = uni(L.t3); u.u = uni(L.u); u.spec = uni(L.spec);
+  u.t3 = uni(L.t3); u.u = uni(L.u); u.spec = uni(L.spec); u.binv = uni(L.binv);
   return u;
 }
 
@@ -1417,6 +1418,58 @@ __device__ void coarse_direct(int nx, gptr<const double> w, gptr<const double> w
   __syncthreads();
 }
 
+// Bed-line step of a forward smoothing pair (option bed_line): the bed row solved exactly with
+// the other rows held, x_M <- L_b^-1 (f_M + q s), s = sum_{l<M} (D_sigma)_Ml x_l,
+// q = h_x sigma_x^old[M] + 1/d_old (the bed row of A x with the bed unknowns moved to the left
+// side). g = f_M + q s is staged in LDS; L.binv holds L_b^-1 transposed, read coalesced.
+template <typename T, int NZ>
+__device__ void bed_step(const Ctx<T>& c, const Lev<T>& L) {
+  constexpr int M = NZ - 1;
+  const int nx = c.nx;
+  T* g = reinterpret_cast<T*>(fft_buf<T>());
+  const T sgm = L.sig[M];
+  for (int i = tid(); i < nx; i += nthr()) {
+    T s = T(0);
+#pragma unroll
+    for (int l = 0; l < M; ++l) s += L.Ds[M * NZ + l] * L.x[l * nx + i];
+    const T q = c.g.hx[i] * (c.g.ao[i] + c.g.bo[i] * sgm) + c.g.ido[i];
+    g[i] = L.f[M * nx + i] + q * s;
+  }
+  __syncthreads();
+  for (int i = tid(); i < nx; i += nthr()) {
+    T acc = T(0);
+    for (int k = 0; k < nx; ++k) acc += L.binv[(int64_t)k * nx + i] * g[k];
+    L.x[M * nx + i] = acc;
+  }
+  __syncthreads();
+}
+
+// The transposed cycle's bed-line step (before its mode step): x_M += L_b^-T (f - A^T x)_M,
+// from x = 0 when xzero (then x is zero-filled first).
+template <typename T, int NZ>
+__device__ void bed_step_T(const Ctx<T>& c, const Lev<T>& L, bool xzero) {
+  constexpr int M = NZ - 1;
+  const int nx = c.nx;
+  gptr<const T> r = gptr<const T>(L.f);
+  if (xzero) {
+    for (int e = tid(); e < NZ * nx; e += nthr()) L.x[e] = T(0);
+    __syncthreads();
+  } else {
+    op_any<T, NZ, true>(c, L, FIN_RESID, gptr<const T>(L.x), L.r, gptr<const T>(L.f),
+                        gptr<T>(nullptr), T(0), false, false, gptr<T>(nullptr));
+    r = gptr<const T>(L.r);
+  }
+  T* g = reinterpret_cast<T*>(fft_buf<T>());
+  for (int i = tid(); i < nx; i += nthr()) g[i] = r[M * nx + i];
+  __syncthreads();
+  for (int i = tid(); i < nx; i += nthr()) {
+    T acc = T(0);
+    for (int k = 0; k < nx; ++k) acc += L.binv[(int64_t)i * nx + k] * g[k];
+    L.x[M * nx + i] += acc;
+  }
+  __syncthreads();
+}
+
 // The V-cycle (paper Alg. 1) from a zero guess on the levels l, l+1, ..., whose row counts are
 // NZ, (NZ+1)/2, ..., 3 (the order halves per level). lev(l) returns the Lev of level l; input
 // lev(l).f, output lev(l).x.
@@ -1444,6 +1497,7 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   o.nu1 = uni(o_.nu1); o.nu2 = uni(o_.nu2); o.coarse_pairs = uni(o_.coarse_pairs);
   o.restart = uni(o_.restart); o.omega_c = uni(o_.omega_c); o.omega_m = uni(o_.omega_m);
   o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle); o.coarse_exact = uni(o_.coarse_exact);
+  o.bed_line = uni(o_.bed_line);
   const int nx = c.nx;
   const T wc = T(o.omega_c), wm = T(o.omega_m);
   const Lev<T> L = uni(lev(l));
@@ -1471,6 +1525,11 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
     if constexpr (NZ > 3 && !TR) {
       if (kind == DOWN) fc = uni(lev(l + 1)).f;
     }
+    // the transposed pair starts with the transposed bed-line step
+    if (TR && o.bed_line && L.binv && kind == MODE) {
+      bed_step_T<T, NZ>(c, L, xzero);
+      xzero = false;
+    }
     if (!xzero)
       op_any<T, NZ, TR>(c, L, kind == COL ? FIN_COLSTEP : FIN_RESID, L.x, L.r, L.f, L.x, wc,
                         !TR && t1x, !TR && kind == COL, fc);
@@ -1491,6 +1550,8 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
       __syncthreads();
       rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.fftb, L.spec, Axpy<T>{L.x, nx, wm, !xzero});
       xzero = false;
+      // the forward pair ends with the bed-line step
+      if (!TR && o.bed_line && L.binv) bed_step<T, NZ>(c, L);
     } else {
       if constexpr (NZ > 3) {
         constexpr int NZC = (NZ + 1) / 2;
@@ -1532,6 +1593,7 @@ __device__ __noinline__ void fmg(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
   o.nu1 = uni(o_.nu1); o.nu2 = uni(o_.nu2); o.coarse_pairs = uni(o_.coarse_pairs);
   o.restart = uni(o_.restart); o.omega_c = uni(o_.omega_c); o.omega_m = uni(o_.omega_m);
   o.adapt = uni(o_.adapt); o.cycle = uni(o_.cycle); o.coarse_exact = uni(o_.coarse_exact);
+  o.bed_line = uni(o_.bed_line);
   if constexpr (NZ == 3) {
     vcycle<T, NZ, LP, false>(c, lev, l, o);
   } else {

@@ -64,6 +64,8 @@ __device__ Lev<T> make_lev(char* ws, const LevelDesc& d) {
   L.t1 = gmp<T>(ws, d.t1); L.t2 = gmp<T>(ws, d.t2); L.t3 = gmp<T>(ws, d.t3);
   L.u = gmp<T>(ws, d.u);
   L.spec = gmp<cpx<T>>(ws, d.spec);
+  const int64_t bo = pr == 0 ? d.bedinv : d.bedinv32;
+  L.binv = bo ? gcp<T>(ws, bo) : gptr<const T>(nullptr);
   return L;
 }
 

@@ -11,7 +11,9 @@ constexpr int kMaxLev = 5;          // orders 32, 16, 8, 4, 2
 constexpr int kMaxRestart = 32;     // FGMRES restart length bound (Hessenberg lives in LDS)
 constexpr int kFftBytes = 32768;    // one LDS ping-pong buffer of the row FFTs
 constexpr int kMaxNz = 33;
-constexpr int kCoarseExactMaxNx = 512;   // largest Nx of the direct coarsest-level solve
+constexpr int kCoarseExactMaxNx = 512;
+// Largest Nx of the bed-line step (its set-up is Nx^3 multiply-adds per level).
+constexpr int kBedLineMaxNx = 1024;   // largest Nx of the direct coarsest-level solve
 
 enum : int32_t { PREC64 = 0, PREC32 = 1 };
 
@@ -29,6 +31,8 @@ struct LevelDesc {
   int64_t x, f, r, t1, t2, t3;      // level vectors [nz][nx] (V-cycle precision)
   int64_t u;                        // full-multigrid iterate of the level [nz][nx]
   int64_t spec;                     // packed row spectra [(nz+1)/2][nx] complex (V precision)
+  int64_t bedinv;                   // bed-line inverse L_b^-1, transposed [nx][nx], float64
+  int64_t bedinv32;                 // its float32 copy (mixed plans; 0 otherwise)
 };
 
 struct TankDesc {
@@ -65,6 +69,7 @@ struct KOpts {
   int32_t adapt;                    // scale omega_m by the tank's factor (scal + 24)
   int32_t cycle;                    // preconditioner: 0 V-cycle, 1 full multigrid
   int32_t coarse_exact;             // coarsest level: 0 smoothing pairs, 1 direct solve
+  int32_t bed_line;                 // end every smoothing pair with the bed-line step
 };
 
 }  // namespace pmgw

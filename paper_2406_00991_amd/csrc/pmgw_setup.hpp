@@ -383,3 +383,139 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_setup(const TankDesc*
 }
 
 }  // namespace pmgw
+
+namespace pmgw {
+
+// ----------------------------------------------------------------------------- bed line
+//
+// Inverse of the bed row's own block of the operator on level l (the bed-line step of the
+// smoother): L_b = -(diag(h_x) D_x + diag(q (D_sigma)_MM)), q = h_x sigma_x^old[M] + 1/d_old,
+// Nx x Nx, D_x circulant with first column c1 = D_x e_0 (the operator's FFT derivative). One
+// workgroup per (tank, level): assemble L_b in the tank's float64 buffer, invert it in place by
+// Gauss-Jordan with partial pivoting (pivot row and column in LDS), undo the pivoting, store the
+// transpose in place (the apply reads it coalesced) and, for mixed plans, a float32 copy. A zero
+// or non-finite pivot marks the tank ENAN.
+
+constexpr int kBedLineThreads = 1024;
+
+__global__ void __launch_bounds__(kBedLineThreads) k_bedline_setup(
+    const TankDesc* __restrict__ descs, char* ws) {
+  __shared__ double prow[kBedLineMaxNx];
+  __shared__ double pcol[kBedLineMaxNx];
+  __shared__ double c1[kBedLineMaxNx];
+  __shared__ int piv[kBedLineMaxNx];
+  __shared__ double redv[kBedLineThreads / 64];
+  __shared__ int redi[kBedLineThreads / 64];
+  const TankDesc td = descs[blockIdx.x];
+  const int l = blockIdx.y;
+  const int nx = td.nx;
+  if (l >= td.nlev || nx < 8 || nx > kBedLineMaxNx) return;
+  const LevelDesc& lv = td.lev[l];
+  if (!lv.bedinv) return;
+  int32_t* status = reinterpret_cast<int32_t*>(mp<double>(ws, td.scal) + 2);
+  if (*status != ST_OK) return;
+  const int lane = tid() & 63, wv = tid() >> 6, nw = nthr() >> 6;
+  const int nz = lv.nz, M = nz - 1;
+
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx,
+                 kGeoFftBytes);
+  double* c1p = c1;
+  dx_rows<double>(1, nx, td.log2nx, td.kfac, kGeoFftBytes,
+                  [=](int, int i) { return i == 0 ? 1.0 : 0.0; },
+                  [=](int, int i, double v) { c1p[i] = v; });
+  __syncthreads();
+
+  const double dsmm = cp<double>(ws, lv.ds[0])[M * nz + M];
+  const double sgm = cp<double>(ws, lv.sig[0])[M];
+  const double* G = cp<double>(ws, td.geo64);
+  const double* ao = G + GEO_AO * nx;
+  const double* bo = G + GEO_BO * nx;
+  const double* ido = G + GEO_IDO * nx;
+  const double* hx = G + GEO_HX * nx;
+  double* W = mp<double>(ws, lv.bedinv);
+  const int msk = nx - 1;
+  for (int r = wv; r < nx; r += nw) {
+    const double q = (hx[r] * (ao[r] + bo[r] * sgm) + ido[r]) * dsmm;
+    for (int c = lane; c < nx; c += 64)
+      W[(int64_t)r * nx + c] = -(hx[r] * c1p[(r - c) & msk] + (r == c ? q : 0.0));
+  }
+  __syncthreads();
+
+  bool bad = false;
+  for (int k = 0; k < nx; ++k) {
+    // pivot row: largest |W[t][k]| over t >= k, the smaller row on ties, NaN ranks highest
+    double best = -1.0;
+    int bi = nx;
+    for (int t = k + tid(); t < nx; t += nthr()) {
+      double v = fabs(W[(int64_t)t * nx + k]);
+      if (!(v >= 0.0)) v = INFINITY;
+      if (v > best) { best = v; bi = t; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
+    __syncthreads();
+    best = redv[0];
+    bi = redi[0];
+    for (int q = 1; q < nw; ++q)
+      if (redv[q] > best || (redv[q] == best && redi[q] < bi)) { best = redv[q]; bi = redi[q]; }
+    if (!(best > 0.0) || !isfinite(best) || bi >= nx) { bad = true; break; }
+    const int p = bi;
+    for (int c = tid(); c < nx; c += nthr()) {
+      const double a = W[(int64_t)k * nx + c], b = W[(int64_t)p * nx + c];
+      if (p != k) W[(int64_t)p * nx + c] = a;
+      prow[c] = b;
+    }
+    if (tid() == 0) piv[k] = p;
+    __syncthreads();
+    for (int t = tid(); t < nx; t += nthr()) pcol[t] = (t == k) ? 0.0 : W[(int64_t)t * nx + k];
+    __syncthreads();
+    const double inv = 1.0 / prow[k];
+    for (int t = wv; t < nx; t += nw) {
+      double* row = W + (int64_t)t * nx;
+      if (t == k) {
+        for (int c = lane; c < nx; c += 64) row[c] = (c == k) ? inv : prow[c] * inv;
+      } else {
+        const double fr = pcol[t] * inv;
+        for (int c = lane; c < nx; c += 64) row[c] = (c == k) ? -fr : row[c] - fr * prow[c];
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid() == 0) *status = ST_ENAN;
+    return;
+  }
+  // undo the row pivoting on the columns of the inverse, last pivot first
+  for (int k = nx - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k) {
+      for (int t = tid(); t < nx; t += nthr()) {
+        double* row = W + (int64_t)t * nx;
+        const double a = row[k];
+        row[k] = row[p];
+        row[p] = a;
+      }
+    }
+    __syncthreads();
+  }
+  // transpose in place: W[k][i] = L_b^-1[i][k]
+  for (int e = tid(); e < nx * nx; e += nthr()) {
+    const int r = e / nx, c = e - r * nx;
+    if (r < c) {
+      const double a = W[(int64_t)r * nx + c];
+      W[(int64_t)r * nx + c] = W[(int64_t)c * nx + r];
+      W[(int64_t)c * nx + r] = a;
+    }
+  }
+  if (lv.bedinv32) {
+    __syncthreads();
+    float* W32 = mp<float>(ws, lv.bedinv32);
+    for (int64_t e = tid(); e < (int64_t)nx * nx; e += nthr()) W32[e] = (float)W[e];
+  }
+}
+
+}  // namespace pmgw

@@ -49,7 +49,7 @@ def test_plan_rejects_bad_options_and_precision():
     for bad in (dict(restart=0), dict(restart=33), dict(omega_c=0.0), dict(omega_m=2.0),
                 dict(nu1=-1), dict(threads=100), dict(threads=1024), dict(coarse_exact=2),
                 dict(class_threads={33: 96}), dict(class_threads=[0, 0, 0, 0, 1024]),
-                dict(class_resident={17: 3}), dict(class_resident={9: -1})):
+                dict(class_resident={17: 3}), dict(class_resident={9: -1}), dict(bed_line=2)):
         rc, _ = _create([32], [9], [1.0], opts=pmgw.default_opts(**bad))
         assert rc == pmgw.EINVAL, bad
 
@@ -153,4 +153,13 @@ def test_per_class_options_are_accepted_and_placed_by_row_count():
     assert list(o.class_resident) == [0, 0, 2, 1, 0]
     rc, h = _create([32, 64, 256], [9, 17, 33], [1.0, 2.0, 3.0], opts=o)
     assert rc == pmgw.OK and h.value
+    pmgw.lib().pmgw_plan_destroy(h)
+
+
+def test_bed_line_size_limit():
+    o = pmgw.default_opts(bed_line=1)
+    rc, _ = _create([2048], [9], [1.0], opts=o)
+    assert rc == pmgw.EINVAL and "1024" in pmgw.lib().pmgw_last_error().decode()
+    rc, h = _create([1024], [9], [1.0], opts=o)
+    assert rc == pmgw.OK
     pmgw.lib().pmgw_plan_destroy(h)

@@ -432,3 +432,76 @@ def test_solve_coarse_exact(case, precision):
               f"smoothing-coarse {bi[0]}, delta {delta:.2e}", flush=True)
         assert inf[1] == 0 and inf[2] <= rtol
         assert delta <= (rtol if precision == "fp64" else 1e-10)
+
+
+BED_CASES = {
+    "steep_128x5": lambda: [wl.manufactured_sloped(128, 5)],
+    "moving_32x9_and_64x17": lambda: [mixed_geometry(wl.manufactured_sloped(32, 9)),
+                                      mixed_geometry(wl.manufactured_sloped(64, 17))],
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", sorted(BED_CASES))
+def test_vcycle_bed_line_parity(case, precision):
+    """pmg_vcycle with the bed-line step (the bed row solved exactly along x at the end of every
+    smoothing pair) against the oracle's cycle with bed_line; float64 1e-12, mixed 2e-3 (the
+    float32 cycle); the cycle without the step is more than 100 times farther away."""
+    probs = BED_CASES[case]()
+    plan = make_plan(probs, precision, bed_line=1)
+    Z = download(plan, plan.vcycle(upload2d(probs, "b")))
+    tol = 1e-12 if precision == "fp64" else 2e-3
+    for pr, got in zip(probs, Z):
+        go, gn = geoms(pr)
+        ref = pmg.Hierarchy(pr["nx"], pr["nz"] - 1, go, gn, pmg.PmgOptions(bed_line=True))(pr["b"])
+        other = pmg.Hierarchy(pr["nx"], pr["nz"] - 1, go, gn, pmg.PmgOptions())(pr["b"])
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        sep = np.linalg.norm(other - ref) / np.linalg.norm(ref)
+        print(f"{case} {precision} {pr['nx']}x{pr['nz']}: bed-line vcycle rel err {err:.2e} "
+              f"(cycle without the step differs by {sep:.2e})", flush=True)
+        assert err <= tol
+        assert sep > 100 * max(err, 1e-14)
+
+
+def test_fmg_and_adjoint_cycle_bed_line():
+    """Full multigrid with the bed-line step against the oracle's (float64, 1e-12), and the
+    transposed cycle (bed-line step first in each transposed pair): <M a, b> = <a, M^T b>."""
+    from paper_2406_00991_amd import pmgw
+    probs = [mixed_geometry(wl.manufactured_sloped(64, 9))]
+    plan = make_plan(probs, "fp64", bed_line=1)
+    z = plan.field()
+    pmgw.fmg(plan, upload2d(probs, "b"), z)
+    pr = probs[0]
+    go, gn = geoms(pr)
+    H = pmg.Hierarchy(pr["nx"], pr["nz"] - 1, go, gn, pmg.PmgOptions(bed_line=True, cycle="FMG"))
+    ref = H.fmg(pr["b"])
+    got = download(plan, z)[0]
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12
+    rng = np.random.default_rng(6)
+    a = upload2d([dict(pr, a=rng.standard_normal((pr["nz"], pr["nx"])))], "a")
+    b = upload2d([dict(pr, a=rng.standard_normal((pr["nz"], pr["nx"])))], "a")
+    Ma, MTb = plan.field(), plan.field()
+    pmgw.pmg_vcycle(plan, a, Ma)
+    pmgw.adjoint_vcycle(plan, b, MTb)
+    lhs, rhs = float((Ma * b).sum()), float((a * MTb).sum())
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + float(Ma.norm() * b.norm()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_steep_bed_solve_with_bed_line(precision):
+    """The sloped manufactured problem at 256 x 5 (max|h_x| kappa_max / M^2 = 1.2, where the
+    cycle without the bed-line step amplifies the error): with the step FGMRES reaches 1e-10 in a
+    few iterations and the solution matches the oracle's dense solve; the iteration count without
+    the step is printed."""
+    probs = [wl.manufactured_sloped(256, 5)]
+    pr = probs[0]
+    ref = op.solve_dense(pr["b"], *geoms(pr))
+    plan = make_plan(probs, precision, bed_line=1)
+    p, info = plan.solve(upload2d(probs, "b"), rtol=1e-10, maxit=100)
+    base = make_plan(probs, precision)
+    _, binfo = base.solve(upload2d(probs, "b"), rtol=1e-10, maxit=100)
+    delta = np.linalg.norm(download(plan, p)[0] - ref) / np.linalg.norm(ref)
+    print(f"steep 256x5 {precision}: iterations with bed line {info[0][0]}, without {binfo[0][0]} "
+          f"(status {binfo[0][1]}), delta {delta:.2e}", flush=True)
+    assert info[0][1] == 0 and info[0][0] <= 15
+    assert delta <= 1e-9
