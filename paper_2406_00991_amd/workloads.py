@@ -97,6 +97,37 @@ def manufactured_sloped(nx=32, nz=9, amp=0.05, bed=0.15, kwave=1.0):
                 eta_new=eta.copy(), b=b, exact=exact)
 
 
+def manufactured3d(nx=16, ny=16, nz=9, amp=0.05, bed=0.15, kx=1.0, ky=1.0):
+    """3D tank (x, y periodic on 2 pi x 2 pi) with a sloped bed and a wavy surface, and the
+    harmonic exact solution p = cos(kx x) cos(ky y) cosh(k (z + 1)), k = sqrt(kx^2 + ky^2).
+
+    h = 1 - bed sin x cos y, eta = amp cos x cos y. Surface row: p at z = eta; interior rows: 0;
+    bed row: the outward normal flux -(h_x p_x + h_y p_y + p_z) at z = -h. Fields [nz][ny][nx].
+    """
+    L = 2.0 * math.pi
+    x = np.arange(nx) * L / nx
+    y = np.arange(ny) * L / ny
+    X, Y = np.meshgrid(x, y)
+    sigma = 0.5 * (1.0 + np.cos(np.arange(nz) * math.pi / (nz - 1)))
+    k = math.hypot(kx, ky)
+    h = 1.0 - bed * np.sin(X) * np.cos(Y)
+    hx = -bed * np.cos(X) * np.cos(Y)
+    hy = bed * np.sin(X) * np.sin(Y)
+    eta = amp * np.cos(X) * np.cos(Y)
+    d = h + eta
+    z = sigma[:, None, None] * d[None] - h[None]
+    exact = np.cos(kx * X)[None] * np.cos(ky * Y)[None] * np.cosh(k * (z + 1.0))
+    zb = -h
+    px = -kx * np.sin(kx * X) * np.cos(ky * Y) * np.cosh(k * (zb + 1.0))
+    py = -ky * np.cos(kx * X) * np.sin(ky * Y) * np.cosh(k * (zb + 1.0))
+    pz = k * np.cos(kx * X) * np.cos(ky * Y) * np.sinh(k * (zb + 1.0))
+    b = np.zeros((nz, ny, nx))
+    b[0] = exact[0]
+    b[nz - 1] = -(hx * px + hy * py + pz)
+    return dict(name="manufactured3d", nx=nx, ny=ny, nz=nz, Lx=L, Ly=L, h=h, eta_old=eta,
+                eta_new=eta.copy(), b=b, exact=exact)
+
+
 def airy_pressure(nx=16, nz=17, depth=1.0, amp=1e-3, mode=2):
     """Linear (Airy) pressure problem on a flat geometry (surface held at z = 0).
 
