@@ -36,6 +36,7 @@ UNITS = [
     ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=1"]),
     ("pmgw_solve.hip", ["-DPMGW_TV=float", "-DPMGW_TR=0", "-DPMGW_WIDE"]),
     ("pmgw_solve.hip", ["-DPMGW_TV=double", "-DPMGW_TR=0", "-DPMGW_WIDE"]),
+    ("pmgw3d.hip", []),
     ("pmgw_stage.hip", ["-DPMGW_STAGE_PART=0"]),
     ("pmgw_stage.hip", ["-DPMGW_STAGE_PART=1"]),
 ]

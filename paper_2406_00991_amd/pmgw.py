@@ -88,6 +88,21 @@ def lib():
         L.pmgw_last_error.restype = ctypes.c_char_p
         L.poisson_solve_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double,
                                             ctypes.c_int32, ctypes.POINTER(Info), _vp]
+        L.pmgw3_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32] + \
+            [ctypes.POINTER(ctypes.c_int32)] * 3 + [_dp, _dp, ctypes.c_int32,
+                                                   ctypes.POINTER(Opts), _vp]
+        L.pmgw3_workspace_bytes.argtypes = [_vp]
+        L.pmgw3_workspace_bytes.restype = ctypes.c_size_t
+        L.pmgw3_bind_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.pmgw3_field_offsets.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64)]
+        L.pmgw3_set_geometry.argtypes = [_vp, _vp, _vp, _vp]
+        L.pmgw3_laplacian_apply.argtypes = [_vp, _vp, _vp]
+        L.pmgw3_vcycle.argtypes = [_vp, _vp, _vp]
+        L.pmgw3_poisson_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                          ctypes.POINTER(Info), _vp]
+        L.pmgw3_plan_destroy.argtypes = [_vp]
+        L.pmgw3_plan_destroy.restype = None
         L.pmgw_profile.argtypes = [_vp, ctypes.c_int32]
         L.pmgw_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), _dp, _dp]
         _lib = L
@@ -405,3 +420,94 @@ def read_info(buf):
     raw = host.view(np.int32).reshape(-1, 4)
     rel = host.reshape(-1, 2)[:, 1]
     return [dict(iters=int(r[0]), status=int(r[1]), relres=float(x)) for r, x in zip(raw, rel)]
+
+
+class Plan3:
+    """A plan for 3D tanks (x, y periodic Fourier, sigma Chebyshev; float64): sizes nx[t], ny[t],
+    nz[t], periods Lx[t], Ly[t]. Fields are [Nz][Ny][Nx] per tank, packed at off3d; h and eta are
+    [Ny][Nx] at off2d. The workspace is a torch uint8 tensor owned by the plan."""
+
+    def __init__(self, nx, ny, nz, Lx, Ly, opts=None, device=None, stream=None):
+        import torch
+        seq = lambda v, f: [f(a) for a in (v if hasattr(v, "__len__") else [v])]
+        nx, ny, nz = seq(nx, int), seq(ny, int), seq(nz, int)
+        Lx, Ly = seq(Lx, float), seq(Ly, float)
+        if not (len(nx) == len(ny) == len(nz) == len(Lx) == len(Ly)):
+            raise PmgwError(EINVAL, "nx, ny, nz, Lx and Ly must have the same length")
+        self.ntanks = len(nx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.opts = opts if opts is not None else default_opts()
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        sh = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        h = ctypes.c_void_p()
+        arr = lambda t, v: (t * self.ntanks)(*v)
+        _check(lib().pmgw3_plan_create(ctypes.byref(h), self.ntanks, arr(ctypes.c_int32, nx),
+                                       arr(ctypes.c_int32, ny), arr(ctypes.c_int32, nz),
+                                       arr(ctypes.c_double, Lx), arr(ctypes.c_double, Ly), FP64,
+                                       ctypes.byref(self.opts), sh))
+        self._h = h
+        o3 = (ctypes.c_int64 * (self.ntanks + 1))()
+        o2 = (ctypes.c_int64 * (self.ntanks + 1))()
+        _check(lib().pmgw3_field_offsets(h, o3, o2))
+        self.off3d, self.off2d = list(o3), list(o2)
+        self.n3d, self.n2d = self.off3d[-1], self.off2d[-1]
+        self.device = device if device is not None else "cuda"
+        self.device_index = None
+        if torch.cuda.is_available():
+            dv = torch.device(self.device)
+            self.device_index = dv.index if dv.index is not None else torch.cuda.current_device()
+        self.ws = torch.empty(int(lib().pmgw3_workspace_bytes(h)), dtype=torch.uint8,
+                              device=self.device)
+        _check(lib().pmgw3_bind_workspace(h, _ptr(self.ws, device=self.device_index),
+                                          self.ws.numel()))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                lib().pmgw3_plan_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def field(self, fill=0.0):
+        import torch
+        return torch.full((self.n3d,), fill, dtype=torch.float64, device=self.device)
+
+    def split3d(self, flat):
+        return [flat[self.off3d[t]:self.off3d[t + 1]].view(self.nz[t], self.ny[t], self.nx[t])
+                for t in range(self.ntanks)]
+
+    def _f(self, *items):
+        return _ptrs([(t, _torch_f64(), n) for t, n in items], self.device_index)
+
+    def set_geometry(self, h, eta_old, eta_new=None):
+        eta_new = eta_old if eta_new is None else eta_new
+        self._geo = (h, eta_old, eta_new)
+        _check(lib().pmgw3_set_geometry(self._h, *self._f((h, self.n2d), (eta_old, self.n2d),
+                                                          (eta_new, self.n2d))))
+
+    def apply(self, p, out=None):
+        out = self.field() if out is None else out
+        _check(lib().pmgw3_laplacian_apply(self._h, *self._f((p, self.n3d), (out, self.n3d))))
+        return out
+
+    def vcycle(self, r, out=None):
+        out = self.field() if out is None else out
+        _check(lib().pmgw3_vcycle(self._h, *self._f((r, self.n3d), (out, self.n3d))))
+        return out
+
+    def solve(self, b, p=None, rtol=1e-10, maxit=100):
+        """FGMRES from the initial guess p (zero when None); returns (p, [(iters, status, relres)])."""
+        p = self.field() if p is None else p
+        infos = (Info * self.ntanks)()
+        rc = lib().pmgw3_poisson_solve(self._h, *self._f((b, self.n3d), (p, self.n3d)),
+                                       ctypes.c_double(rtol), int(maxit), infos, None)
+        _check(rc, soft_ok=True)
+        return p, [(i.iters, i.status, i.relres) for i in infos]
+
+
+def _torch_f64():
+    import torch
+    return torch.float64

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "pmgw.h")).read()
+    import glob
+    txt = "\n".join(open(f).read() for f in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b([a-z_0-9]+)\s*\(", txt)) - {"if", "sizeof"})
 
@@ -20,7 +21,8 @@ def _declared():
 def test_library_loads_and_exports_every_declared_symbol():
     L = pmgw.lib()
     names = _declared()
-    assert {"laplacian_apply", "pmg_vcycle", "poisson_solve", "rk4_stage"} <= set(names)
+    assert {"laplacian_apply", "pmg_vcycle", "poisson_solve", "rk4_stage",
+            "pmgw3_poisson_solve"} <= set(names)
     for n in names:
         assert hasattr(L, n), n
 
@@ -163,3 +165,41 @@ def test_bed_line_size_limit():
     rc, h = _create([1024], [9], [1.0], opts=o)
     assert rc == pmgw.OK
     pmgw.lib().pmgw_plan_destroy(h)
+
+
+def _create3(nx, ny, nz, Lx, Ly, prec=pmgw.FP64):
+    h = ctypes.c_void_p()
+    n = len(nx)
+    arr = lambda t, v: (t * n)(*v)
+    rc = pmgw.lib().pmgw3_plan_create(ctypes.byref(h), n, arr(ctypes.c_int32, nx),
+                                      arr(ctypes.c_int32, ny), arr(ctypes.c_int32, nz),
+                                      arr(ctypes.c_double, Lx), arr(ctypes.c_double, Ly), prec,
+                                      None, None)
+    return rc, h
+
+
+@pytest.mark.parametrize("nx,ny,nz,Lx,Ly,prec", [
+    ([6], [8], [9], [1.0], [1.0], pmgw.FP64), ([8], [2], [9], [1.0], [1.0], pmgw.FP64),
+    ([8], [8], [7], [1.0], [1.0], pmgw.FP64), ([8], [8], [9], [0.0], [1.0], pmgw.FP64),
+    ([8], [8], [9], [1.0], [-1.0], pmgw.FP64), ([512], [256], [9], [1.0], [1.0], pmgw.FP64),
+    ([8], [8], [9], [1.0], [1.0], pmgw.MIXED)])
+def test_plan3_rejects_bad_sizes(nx, ny, nz, Lx, Ly, prec):
+    rc, h = _create3(nx, ny, nz, Lx, Ly, prec)
+    assert rc == pmgw.EINVAL and not h.value
+    assert pmgw.lib().pmgw_last_error()
+
+
+def test_plan3_layout_and_unbound_calls():
+    rc, h = _create3([16, 8], [8, 32], [9, 17], [1.0, 2.0], [3.0, 1.5])
+    assert rc == pmgw.OK
+    L = pmgw.lib()
+    o3 = (ctypes.c_int64 * 3)()
+    o2 = (ctypes.c_int64 * 3)()
+    assert L.pmgw3_field_offsets(h, o3, o2) == pmgw.OK
+    assert list(o3) == [0, 16 * 8 * 9, 16 * 8 * 9 + 8 * 32 * 17]
+    assert list(o2) == [0, 128, 128 + 256]
+    assert L.pmgw3_workspace_bytes(h) > 0
+    # no workspace bound yet: every compute call is refused before touching the device
+    assert L.pmgw3_laplacian_apply(h, None, None) == pmgw.EWORKSPACE
+    assert L.pmgw3_set_geometry(h, None, None, None) == pmgw.EWORKSPACE
+    L.pmgw3_plan_destroy(h)
