@@ -265,6 +265,35 @@ def run_bar(seeds, reps, rtol):
     return out
 
 
+# ----------------------------------------------------------------------------- 3D tank
+def run_tank3d(nx=64, ny=64, nz=17, reps=3, rtol=1e-10):
+    """A 3D tank (x, y periodic Fourier, sigma Chebyshev; float64): the manufactured problem on a
+    sloped bed under a moving wavy surface, solved from zero; mean of `reps` solves timed with
+    events on the plan's stream."""
+    import torch
+
+    from paper_2406_00991_amd import pmgw
+    from paper_2406_00991_amd import workloads as wl
+    pr = wl.manufactured3d(nx, ny, nz)
+    plan = pmgw.Plan3([nx], [ny], [nz], [pr["Lx"]], [pr["Ly"]])
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64,
+                                 device="cuda")
+    plan.set_geometry(dev(pr["h"]), dev(pr["eta_old"]), dev(1.05 * pr["eta_new"]))
+    b = dev(pr["b"])
+    _, info = plan.solve(b, rtol=rtol)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        plan.solve(b, plan.field(), rtol=rtol)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"workload": f"3D tank {nx}x{ny}x{nz}, sloped bed, moving surface, float64, rtol {rtol:g}",
+            "value": 1e3 / ms, "unit": "solves/s", "mean_solve_ms": ms, "iters": info[0][0],
+            "relres": info[0][2], "cus_used": 1}
+
+
 # ----------------------------------------------------------------------------- oracle timing
 def _cores():
     try:
@@ -353,6 +382,8 @@ def main():
                     help="skip the 512-tank batched solve reported beside the headline")
     ap.add_argument("--no-bar", action="store_true",
                     help="skip the 1024 x 33 bar solves reported beside the headline")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the 3D tank solve reported beside the headline")
     ap.add_argument("--calibrate-mib", type=int, default=0,
                     help="first run an elementwise negation of a float64 buffer of this size "
                          "(reads and writes it once), the known-traffic kernel that scales the "
@@ -443,6 +474,9 @@ def main():
         out["bar"] = run_bar([0, 1, 2, 3, 4], 5, rtol)
         print(f"# bar: mixed {out['bar']['mixed']['value']:.0f} solves/s, fp64 "
               f"{out['bar']['fp64']['value']:.0f} solves/s", file=sys.stderr, flush=True)
+    if not args.no_3d:
+        out["tank3d"] = run_tank3d()
+        print(f"# 3D tank: {out['tank3d']['value']:.1f} solves/s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wave)
     print(json.dumps(out))
