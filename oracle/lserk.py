@@ -21,6 +21,19 @@ Oracle (test infrastructure only).
      u <- u + beta K_u, w <- w + beta K_w. Here Div^new(u, w) vanishes inside (to the solver
      tolerance) and n . u = 0 on the bed.
   7. filter u and w in x and sigma (Sec. 3.6); K is not filtered.
+
+Two model options (``Physics``), for the oscillatory boundary-layer case (Sec. 5, oscillatory wave
+boundary layer):
+- ``linear``: the linearised equations (eq. NSElin with eq. linFS): no advection terms in F_u, F_w
+  (the sigma_t mesh-velocity term, second order in the amplitude, goes with them),
+  eta_t = w~, and the sigma-map held on the still-water domain (d = h, metrics of eta = 0 for
+  both the old and the new geometry), so the boundary conditions sit at z = 0.
+- ``no_slip``: u = 0 on the bed (the paper's no-slip condition) for both velocity components.
+  The bed row of the pressure problem keeps its form: with the bed rows of u and K zero at the
+  stage start, the provisional bed velocity is beta dt (F_u, F_w), so the Neumann datum is the
+  normal component of the momentum forcing, viscous stress included. After the update and the
+  filter the bed rows of u, w, K_u and K_w are set to zero (the projection cannot remove the
+  tangential slip by itself).
 """
 from dataclasses import dataclass
 from fractions import Fraction
@@ -74,6 +87,8 @@ class Physics:
     filt_s: float = 2.0
     filt_fx: float = 0.5
     filt_fz: float = 0.9
+    linear: bool = False
+    no_slip: bool = False
 
 
 @dataclass
@@ -107,9 +122,15 @@ def forcing(u, w, eta, eta_t, g_old, ph):
     sx = g_old.sigma_x(sig)
     st = -sig[:, None] * (eta_t * g_old.inv_d)[None, :]
     ws = st + u * sx + w * g_old.inv_d[None, :]
-    lap = lambda f: op.div(*op.grad(f, g_old, M), g_old, M)
-    Fu = -u * sp.dx(u, L) - ws * (Ds @ u) - ph.g * sp.dx(eta, L)[None, :] + ph.nu * lap(u)
-    Fw = -u * sp.dx(w, L) - ws * (Ds @ w) + ph.nu * lap(w)
+    def visc(f):
+        v = ph.nu * op.div(*op.grad(f, g_old, M), g_old, M)
+        if ph.no_slip:
+            v[0] = 0.0
+        return v
+    if ph.linear:
+        return -ph.g * sp.dx(eta, L)[None, :] + visc(u), visc(w)
+    Fu = -u * sp.dx(u, L) - ws * (Ds @ u) - ph.g * sp.dx(eta, L)[None, :] + visc(u)
+    Fw = -u * sp.dx(w, L) - ws * (Ds @ w) + visc(w)
     return Fu, Fw
 
 
@@ -132,11 +153,18 @@ def stage(k, dt, h, L, s, solve, ph=None):
     a, bcoef = ALPHA[k - 1], BETA[k - 1]
     M = s.u.shape[0] - 1
     eta_old = s.eta.copy()
-    g_old = op.Geometry(h, eta_old, L)
-    eta_t = -s.u[0] * sp.dx(eta_old, L) + s.w[0]
+    if ph.linear:
+        eta_t = s.w[0].copy()
+    else:
+        eta_t = -s.u[0] * sp.dx(eta_old, L) + s.w[0]
     s.Keta = a * s.Keta + dt * eta_t
     eta_new = sp.filter_x(eta_old + bcoef * s.Keta, L, ph.filt_fx, ph.filt_alpha, ph.filt_s)
-    g_new = op.Geometry(h, eta_new, L)
+    if ph.linear:
+        g_old = op.Geometry(h, np.zeros_like(eta_old), L)
+        g_new = g_old
+    else:
+        g_old = op.Geometry(h, eta_old, L)
+        g_new = op.Geometry(h, eta_new, L)
     Fu, Fw = forcing(s.u, s.w, eta_old, eta_t, g_old, ph)
     us = s.u + bcoef * (a * s.Ku + dt * Fu)
     ws_ = s.w + bcoef * (a * s.Kw + dt * Fw)
@@ -152,6 +180,9 @@ def stage(k, dt, h, L, s, solve, ph=None):
     div_ref = np.abs(op.div(us, ws_, g_new, M)[1:M]).max()
     s.u = filter_field(u, L, ph)
     s.w = filter_field(w, L, ph)
+    if ph.no_slip:
+        for f in (s.u, s.w, s.Ku, s.Kw):
+            f[M] = 0.0
     s.eta = eta_new
     s.p = p
     return dict(div=div_after, div_ref=div_ref, bed_flux=np.abs(g_old.hx * u[M] + w[M]).max())

@@ -289,3 +289,43 @@ def airy_wave(nx=16, nz=9, depth=1.0, k=1.0, amp=1e-6, cfl=0.5):
     c = om / k
     return dict(name="airy", nx=nx, nz=nz, L=L, h=h, eta=eta, u=u, w=w, omega=om,
                 period=2.0 * math.pi / om, dt=cfl * (L / nx) / c, amp=amp, k=k)
+
+
+def stokes_layer(nx=16, nz=33, depth=0.1, H=0.02, kh=0.6725, nu=1e-6, steps_per_period=40):
+    """Oscillatory wave boundary layer over a no-slip flat bed (linear wave, periodic domain).
+
+    One wavelength per domain, k h = 0.6725 and H = 0.02 m as in the paper's boundary-layer case;
+    the depth (not stated there) is 0.1 m so that at 33 sigma rows two nodes lie inside the layer
+    thickness 3 pi delta_1 / 4. With theta = omega t - k x, zeta = z + h the height above the bed,
+    delta_1 = (2 nu / omega)^(1/2) and U_0m = pi H / (T sinh kh) the outer velocity amplitude at
+    the bed, ``exact(t)`` gives the linear potential wave with the Stokes-layer correction
+    (``exact(t, layer=False)`` the potential wave alone)
+        u = (pi H / T) cosh(k zeta) / sinh(kh) cos(theta) - U_0m exp(-zeta/delta_1) cos(theta - zeta/delta_1),
+        w = -(pi H / T) sinh(k zeta) / sinh(kh) sin(theta),  eta = (H/2) cos(k x - omega t)
+    (the boundary-layer solution of small-amplitude wave theory; the bed amplitude of the printed
+    U_0m is used). The initial state is exact(0) with u = w = 0 on the bed row; dt = T /
+    steps_per_period.
+    """
+    k = kh / depth
+    L = 2.0 * math.pi / k
+    om = math.sqrt(G * k * math.tanh(kh))
+    T = 2.0 * math.pi / om
+    d1 = math.sqrt(2.0 * nu / om)
+    U0m = math.pi * H / (T * math.sinh(kh))
+    x, sigma = nodes(nx, nz, L)
+    zeta = sigma[:, None] * depth * np.ones((1, nx))
+
+    def exact(t, layer=True):
+        th = om * t - k * x[None, :]
+        u = (math.pi * H / T) * np.cosh(k * zeta) / math.sinh(kh) * np.cos(th)
+        if layer:
+            u = u - U0m * np.exp(-zeta / d1) * np.cos(th - zeta / d1)
+        w = -(math.pi * H / T) * np.sinh(k * zeta) / math.sinh(kh) * np.sin(th)
+        return u, w, (H / 2.0) * np.cos(k * x - om * t)
+
+    u, w, eta = exact(0.0)
+    u[-1] = 0.0
+    w[-1] = 0.0
+    return dict(name="stokes_layer", nx=nx, nz=nz, L=L, h=np.full(nx, depth), u=u, w=w, eta=eta,
+                dt=T / steps_per_period, T=T, omega=om, k=k, delta1=d1, U0m=U0m, nu=nu,
+                zeta=zeta, exact=exact)

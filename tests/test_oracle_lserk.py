@@ -1,6 +1,9 @@
 """Pins of the oracle's low-storage Runge-Kutta stage (paper Sec. 3.1-3.3, 3.6) against the
 mathematics: Runge-Kutta order conditions, rest state, the divergence constraint the projection
-enforces, and linear wave theory (dispersion relation, Sec. 5.3)."""
+enforces, and linear wave theory (dispersion relation, Sec. 5.3); the linearised model (eq. NSElin,
+eq. linFS) against linear wave theory at a finite amplitude, and the no-slip bed against the
+closed-form oscillatory boundary layer (Sec. 5, oscillatory wave boundary layer)."""
+import scipy.linalg as sla
 import math
 from fractions import Fraction
 
@@ -179,3 +182,66 @@ def test_forcing_pin_sees_each_term():
     scale = np.abs(want_u).max()
     for name, t in terms.items():
         assert np.abs(t).max() / scale > 1e-3, name
+
+
+def _fixed_operator_solver(nx, M, h, L):
+    """The linearised model's pressure operator is constant: factor it once."""
+    g = op.Geometry(h, np.zeros(nx), L)
+    lu = sla.lu_factor(op.assemble(nx, M, g, g))
+    return lambda b, go, gn, p0: sla.lu_solve(lu, b.ravel()).reshape(b.shape)
+
+
+def _run_layer(periods, **phys):
+    w = wl.stokes_layer(nx=8)
+    M = w["nz"] - 1
+    ph = lserk.Physics(nu=w["nu"], filt_fx=1.0, filt_fz=1.0, linear=True, no_slip=True)
+    for k_, v in phys.items():
+        setattr(ph, k_, v)
+    s = lserk.State.rest_registers(w["u"], w["w"], w["eta"])
+    solve = _fixed_operator_solver(w["nx"], M, w["h"], w["L"])
+    n = int(round(periods * w["T"] / w["dt"]))
+    for _ in range(n):
+        lserk.step(w["dt"], w["h"], w["L"], s, solve, ph)
+    return w, s, n * w["dt"]
+
+
+def test_linear_model_is_airy_at_finite_amplitude():
+    # At H/h = 0.2 the nonlinear model departs from linear theory by tens of percent; the
+    # linearised one (no advection, eta_t = w~, sigma-map on the still-water domain) follows the
+    # Airy wave to the time-stepping error.
+    w = wl.stokes_layer(nx=16, nz=17)
+    M = w["nz"] - 1
+    ph = lserk.Physics(nu=0.0, filt_fx=1.0, filt_fz=1.0, linear=True)
+    u0, w0, e0 = w["exact"](0.0, layer=False)
+    s = lserk.State.rest_registers(u0, w0, e0)
+    solve = _fixed_operator_solver(16, M, w["h"], w["L"])
+    n = int(round(w["T"] / w["dt"]))
+    for _ in range(n):
+        lserk.step(w["dt"], w["h"], w["L"], s, solve, ph)
+    ue, we, ee = w["exact"](n * w["dt"], layer=False)
+    H = 2 * np.abs(e0).max()
+    assert np.abs(s.eta - ee).max() <= 1e-4 * H / 2
+    assert np.abs(s.u - ue).max() <= 1e-4 * np.abs(ue).max()
+    assert np.abs(s.w - we).max() <= 1e-4 * np.abs(ue).max()
+
+
+def test_no_slip_bed_reproduces_the_stokes_layer():
+    w, s, t = _run_layer(0.5)
+    M = w["nz"] - 1
+    assert np.all(s.u[M] == 0.0) and np.all(s.w[M] == 0.0)
+    assert np.all(s.Ku[M] == 0.0) and np.all(s.Kw[M] == 0.0)
+    ue, _, _ = w["exact"](t)
+    near = w["zeta"][:, 0] < 6 * w["delta1"]
+    assert near.sum() >= 4
+    err = np.abs(s.u[near] - ue[near]).max() / w["U0m"]
+    assert err <= 0.03, err
+
+
+@pytest.mark.parametrize("nu", [2e-6, 0.5e-6])
+def test_stokes_layer_pin_sees_the_viscosity(nu):
+    # the closed form at nu = 1e-6 against a model run at twice or half that viscosity: the layer
+    # thickness changes by sqrt(2) and the near-bed profile by far more than the pin's bound
+    w, s, t = _run_layer(0.5, nu=nu)
+    ue, _, _ = w["exact"](t)
+    near = w["zeta"][:, 0] < 6 * w["delta1"]
+    assert np.abs(s.u[near] - ue[near]).max() / w["U0m"] > 0.1
