@@ -84,6 +84,12 @@ typedef struct {
                                fits, 2 = global-memory cycle [0]                            */
     int32_t bed_line;       /* 1 = end every smoothing pair with the bed-line step below
                                (Nx <= 1024; the V-cycle then runs in global memory) [0]     */
+    int32_t linear;         /* rk4_stage model: 1 = the linearised equations of the paper's
+                               small-amplitude analysis (eq. NSElin, eq. linFS): no advection,
+                               eta_t = w at the surface, sigma-map held on the still-water
+                               domain (the plan's geometry is set with eta = 0) [0]          */
+    int32_t no_slip;        /* rk4_stage bed: 1 = no-slip bed u = w = 0 (paper Sec. 5,
+                               oscillatory wave boundary layer), see rk4_stage [0]           */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */
@@ -196,7 +202,14 @@ int poisson_solve(pmgw_plan plan, const double* b, double* p, double rtol, int32
  * fields; h, eta, Keta device 1D fields; all are updated in place except h. On exit p holds
  * the stage's dynamic pressure p_D^(k-1). The K registers need no reset between steps
  * (stage 1 multiplies them by alpha_1 = 0) but must hold finite values. The workspace keeps
- * the stage's intermediate fields; the plan's geometry is left at (eta^(k-1), eta^(k)).
+ * the stage's intermediate fields; the plan's geometry is left at (eta^(k-1), eta^(k)), or at
+ * the still-water geometry (eta = 0) with opts.linear.
+ * With opts.no_slip the bed rows of u, w, Ku and Kw are set to zero after the update and the
+ * filter; the bed row of the pressure problem keeps its form (with zero bed velocity at the
+ * stage start its datum is the normal component of the momentum forcing, viscous stress
+ * included), and the viscous term is left out on the surface row, for which the paper gives no
+ * stress condition (the surface row moves by the inviscid momentum equation). Pass a state whose
+ * bed rows of u, w, Ku, Kw are zero.
  */
 int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, double* w,
               double* eta, double* Ku, double* Kw, double* Keta, double* p, double rtol,
@@ -235,7 +248,8 @@ int pmgw_adjoint_solve(pmgw_plan plan, const double* g, double* lambda, double r
  * info_dev (device, nullable) holds 2 x ntanks records: entries [0, ntanks) receive the forward
  * recompute solve's outcome per tank, entries [ntanks, 2 ntanks) the adjoint solve's. The forward
  * solve is differentiated as exact.
- * The plan's geometry is left at the stage's (eta^(k-1), eta^(k)).
+ * The plan's geometry is left at the stage's (eta^(k-1), eta^(k)). Plans created with
+ * opts.linear or opts.no_slip are refused (PMGW_EINVAL): the adjoint covers the default model.
  */
 int rk4_stage_adjoint(pmgw_plan plan, int32_t k, double dt, const double* h, const double* u,
                       const double* w, const double* eta, const double* Ku, const double* Kw,

@@ -405,6 +405,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   if (o.coarse_exact != 0 && o.coarse_exact != 1)
     return fail(PMGW_EINVAL, "coarse_exact must be 0 or 1");
   if (o.bed_line != 0 && o.bed_line != 1) return fail(PMGW_EINVAL, "bed_line must be 0 or 1");
+  if (o.linear != 0 && o.linear != 1) return fail(PMGW_EINVAL, "linear must be 0 or 1");
+  if (o.no_slip != 0 && o.no_slip != 1) return fail(PMGW_EINVAL, "no_slip must be 0 or 1");
   if (o.resident != 0 && o.resident != 1) return fail(PMGW_EINVAL, "resident must be 0 or 1");
   for (int t = 0; t < ntanks; ++t) {
     const int n = nx[t], M = nz[t] - 1;
@@ -905,10 +907,13 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   cf.rho = p->opts.rho;
   cf.g = p->opts.g;
   cf.nu = p->opts.nu_visc;
+  cf.lin = p->opts.linear;
+  cf.noslip = p->opts.no_slip;
   const RkBufs rb = rk_bufs(p->ws + p->rk_off, p->off2d[p->ntanks], p->off1d[p->ntanks]);
   rc = launch_rk_all(p, 0, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
   if (rc) return rc;
-  rc = pmgw_set_geometry(p, h, rb.eo, eta);
+  // the linearised model keeps the still-water geometry: k_rk_pre leaves rb.z1 at zero
+  rc = cf.lin ? pmgw_set_geometry(p, h, rb.z1, rb.z1) : pmgw_set_geometry(p, h, rb.eo, eta);
   if (rc) return rc;
   rc = launch_rk_all(p, 1, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
   if (rc) return rc;
@@ -985,6 +990,8 @@ extern "C" int rk4_stage_adjoint(pmgw_plan p, int32_t k, double dt, const double
     return fail(PMGW_EINVAL, "fields must be non-NULL");
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(PMGW_EINVAL, "rtol must be positive");
   if (maxit < 1) return fail(PMGW_EINVAL, "maxit must be >= 1");
+  if (p->opts.linear || p->opts.no_slip)
+    return fail(PMGW_EINVAL, "the adjoint stage covers the default model (linear = no_slip = 0)");
   RkCoef cf;
   cf.a = kCkAlpha[k - 1];
   cf.b = kCkBeta[k - 1];

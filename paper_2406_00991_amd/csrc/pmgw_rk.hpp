@@ -12,6 +12,12 @@
 //   (solve)     flexible GMRES / p-multigrid for the dynamic pressure p.
 //   k_rk_post   (G_x, G_z) = Grad^old p; K_u <- a K_u + dt (F_u - G_x/rho), K_w likewise;
 //               u <- filter(u + b K_u), w <- filter(w + b K_w) in x and sigma.
+//
+// Model options (RkCoef): lin = the linearised equations (eq. NSElin, eq. linFS): F without the
+// advection terms, eta_t = w~, and the host sets the geometry with eta = 0 (z1, zeroed by
+// k_rk_pre); noslip = no-slip bed (Sec. 5, oscillatory wave boundary layer): after the update
+// and the filter, K_u, K_w, u and w are set to zero on the bed row, and the viscous term is
+// dropped on the surface row.
 #pragma once
 #include <stdint.h>
 
@@ -21,14 +27,14 @@ namespace pmgw {
 
 // Packed workspace of the stage: 1D arrays of n1d doubles, 2D arrays of n2d doubles.
 struct RkBufs {
-  double *eo, *etat, *etax;
+  double *eo, *etat, *etax, *z1;
   double *Fu, *Fw, *us, *ws, *b, *r1, *r2;
 };
 
 inline int64_t rk_align(int64_t v) { return (v + 255) & ~int64_t(255); }
 
 inline int64_t rk_workspace_bytes(int64_t n2d, int64_t n1d) {
-  return 3 * rk_align(8 * n1d) + 7 * rk_align(8 * n2d);
+  return 4 * rk_align(8 * n1d) + 7 * rk_align(8 * n2d);
 }
 
 inline RkBufs rk_bufs(char* base, int64_t n2d, int64_t n1d) {
@@ -42,6 +48,7 @@ inline RkBufs rk_bufs(char* base, int64_t n2d, int64_t n1d) {
   r.eo = take(8 * n1d);
   r.etat = take(8 * n1d);
   r.etax = take(8 * n1d);
+  r.z1 = take(8 * n1d);
   r.Fu = take(8 * n2d);
   r.Fw = take(8 * n2d);
   r.us = take(8 * n2d);
@@ -54,6 +61,9 @@ inline RkBufs rk_bufs(char* base, int64_t n2d, int64_t n1d) {
 
 struct RkCoef {
   double a, b, dt, rho, g, nu;
+  int lin = 0;     // linearised model: no advection, eta_t = w~, still-water sigma-map
+  int noslip = 0;  // no-slip bed: bed rows of u, w, K_u, K_w held at zero; no viscous term at
+                   // the surface row
 };
 
 // float64 context of a tank: metrics of the geometry last set, finest-level constants; also
@@ -101,13 +111,15 @@ __global__ void __launch_bounds__(256) k_rk_pre(const TankDesc* __restrict__ des
   stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx, fftb);
   dx_rows<double>(1, nx, td.log2nx, td.kfac, fftb, [=](int, int i) { return e[i]; },
                   [=](int, int i, double v) { ex[i] = v; });
+  const gptr<double> z1 = as_global(rb.z1 + td.off1d);
   for (int i = tid(); i < nx; i += nthr()) {
-    const double rate = -u0[i] * ex[i] + w0[i];
+    const double rate = cf.lin ? w0[i] : -u0[i] * ex[i] + w0[i];
     et[i] = rate;
     const double k = cf.a * ke[i] + cf.dt * rate;
     ke[i] = k;
     eo[i] = e[i];
     e[i] = e[i] + cf.b * k;
+    z1[i] = 0.0;
   }
   __syncthreads();
   spectral_rows<double>(1, nx, td.log2nx, fftb, [=](int, int i) { return e[i]; },
@@ -153,7 +165,8 @@ __global__ void __launch_bounds__(256) k_rk_force(const TankDesc* __restrict__ d
       const int j = e / nx, i = e - j * nx;
       const double sx = g.ao[i] + g.bo[i] * sig[j];
       const double wsig = -sig[j] * et[i] * g.ido[i] + uu[e] * sx + wwp[e] * g.ido[i];
-      double fo = -uu[e] * t2[e] - wsig * t1[e] + cf.nu * F[e];
+      double fo = (cf.noslip && j == 0) ? 0.0 : cf.nu * F[e];
+      if (!cf.lin) fo += -uu[e] * t2[e] - wsig * t1[e];
       if (comp == 0) fo -= cf.g * ex[i];
       F[e] = fo;
       star[e] = f[e] + cf.b * (cf.a * K[e] + cf.dt * fo);
@@ -209,8 +222,9 @@ __global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ de
     const double gz = t1[e] * g.ido[i];
     const double a = cf.a * ku[e] + cf.dt * (Fu[e] - gx * ir);
     const double bb = cf.a * kw[e] + cf.dt * (Fw[e] - gz * ir);
-    ku[e] = a;
-    kw[e] = bb;
+    const bool held = cf.noslip && j == NZ - 1;  // the update itself runs unheld, as filtered
+    ku[e] = held ? 0.0 : a;
+    kw[e] = held ? 0.0 : bb;
     r1[e] = uu[e] + cf.b * a;
     r2[e] = wwp[e] + cf.b * bb;
   }
@@ -224,6 +238,10 @@ __global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ de
                           [=](int j, int i, double v) { t3[j * nx + i] = v; });
     col_dsig<double, NZ>(nx, fz, t3, dst);
     __syncthreads();
+    if (cf.noslip) {
+      for (int i = tid(); i < nx; i += nthr()) dst[(NZ - 1) * nx + i] = 0.0;
+      __syncthreads();
+    }
   }
 }
 

@@ -291,12 +291,13 @@ def airy_wave(nx=16, nz=9, depth=1.0, k=1.0, amp=1e-6, cfl=0.5):
                 period=2.0 * math.pi / om, dt=cfl * (L / nx) / c, amp=amp, k=k)
 
 
-def stokes_layer(nx=16, nz=33, depth=0.1, H=0.02, kh=0.6725, nu=1e-6, steps_per_period=40):
+def stokes_layer(nx=64, nz=33, depth=0.1, H=0.02, kh=0.6725, nu=1e-6, steps_per_period=40):
     """Oscillatory wave boundary layer over a no-slip flat bed (linear wave, periodic domain).
 
     One wavelength per domain, k h = 0.6725 and H = 0.02 m as in the paper's boundary-layer case;
     the depth (not stated there) is 0.1 m so that at 33 sigma rows two nodes lie inside the layer
-    thickness 3 pi delta_1 / 4. With theta = omega t - k x, zeta = z + h the height above the bed,
+    thickness 3 pi delta_1 / 4. The wave is a single Fourier mode; Nx = 64 (the paper uses 20)
+    meets the solver's Nx >= 2 (Nz - 1). With theta = omega t - k x, zeta = z + h the height above the bed,
     delta_1 = (2 nu / omega)^(1/2) and U_0m = pi H / (T sinh kh) the outer velocity amplitude at
     the bed, ``exact(t)`` gives the linear potential wave with the Stokes-layer correction
     (``exact(t, layer=False)`` the potential wave alone)

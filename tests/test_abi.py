@@ -51,7 +51,8 @@ def test_plan_rejects_bad_options_and_precision():
     for bad in (dict(restart=0), dict(restart=33), dict(omega_c=0.0), dict(omega_m=2.0),
                 dict(nu1=-1), dict(threads=100), dict(threads=1024), dict(coarse_exact=2),
                 dict(class_threads={33: 96}), dict(class_threads=[0, 0, 0, 0, 1024]),
-                dict(class_resident={17: 3}), dict(class_resident={9: -1}), dict(bed_line=2)):
+                dict(class_resident={17: 3}), dict(class_resident={9: -1}), dict(bed_line=2),
+                dict(linear=2), dict(no_slip=-1)):
         rc, _ = _create([32], [9], [1.0], opts=pmgw.default_opts(**bad))
         assert rc == pmgw.EINVAL, bad
 
