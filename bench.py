@@ -112,13 +112,14 @@ def stored_traffic(kernel, precision):
 class Tank:
     """Device state of one tank and the stage loop through the C ABI."""
 
-    def __init__(self, wave, precision, capacity):
+    def __init__(self, wave, precision, capacity, opts=None):
         import torch
 
         from paper_2406_00991_amd import pmgw
         self.pmgw = pmgw
         self.wave = wave
-        self.plan = pmgw.Plan([wave["nx"]], [wave["nz"]], [wave["L"]], precision=precision)
+        self.plan = pmgw.Plan([wave["nx"]], [wave["nz"]], [wave["L"]], precision=precision,
+                              opts=opts)
         dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64,
                                      device="cuda")
         self.h, self.u, self.w, self.eta = (dev(wave[k]) for k in ("h", "u", "w", "eta"))
@@ -294,6 +295,40 @@ def run_tank3d(nx=64, ny=64, nz=17, reps=3, rtol=1e-10):
             "relres": info[0][2], "cus_used": 1}
 
 
+def run_stokes_layer(precision, warmup=2, rtol=1e-10):
+    """The oscillatory boundary layer (linearised model, no-slip bed, 64 x 33, filters off): one
+    wave period of RK4 steps after `warmup` steps, timed like the headline, and the near-bed
+    velocity against the closed-form Stokes layer at the end."""
+    import torch
+
+    from paper_2406_00991_amd import pmgw
+    from paper_2406_00991_amd import workloads as wl
+    t = wl.stokes_layer()
+    opts = pmgw.default_opts(nu_visc=t["nu"], filt_fx=1.0, filt_fz=1.0, linear=1, no_slip=1)
+    steps = int(round(t["T"] / t["dt"]))
+    T = Tank(t, precision, 5 * (steps + warmup), opts)
+    for _ in range(warmup):
+        T.step(t["dt"], rtol)
+    torch.cuda.synchronize()
+    T.pmgw.profile_start(T.plan, 5 * steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        T.step(t["dt"], rtol)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, tot_ms, _ = T.pmgw.profile_read(T.plan)
+    T.pmgw.profile_start(T.plan, 0)
+    infos = T.infos(5 * warmup, 5 * steps)
+    ue, _, _ = t["exact"]((warmup + steps) * t["dt"])
+    near = t["zeta"][:, 0] < 6 * t["delta1"]
+    u = T.u.cpu().numpy().reshape(t["nz"], t["nx"])
+    return {"value": 5 * steps / wall, "unit": "solves/s", "ms_per_step": 1e3 * wall / steps,
+            "steps": steps, "mean_launch_ms": tot_ms / max(launches, 1),
+            "mean_iters": float(np.mean([i["iters"] for i in infos])),
+            "status": sorted({i["status"] for i in infos}),
+            "closed_form_err": float(np.abs(u[near] - ue[near]).max() / t["U0m"])}
+
+
 # ----------------------------------------------------------------------------- oracle timing
 def _cores():
     try:
@@ -384,6 +419,9 @@ def main():
                     help="skip the 1024 x 33 bar solves reported beside the headline")
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the 3D tank solve reported beside the headline")
+    ap.add_argument("--no-layer", action="store_true",
+                    help="skip the oscillatory boundary-layer stepping reported beside the "
+                         "headline")
     ap.add_argument("--calibrate-mib", type=int, default=0,
                     help="first run an elementwise negation of a float64 buffer of this size "
                          "(reads and writes it once), the known-traffic kernel that scales the "
@@ -477,6 +515,16 @@ def main():
     if not args.no_3d:
         out["tank3d"] = run_tank3d()
         print(f"# 3D tank: {out['tank3d']['value']:.1f} solves/s", file=sys.stderr, flush=True)
+    if not args.no_layer:
+        out["stokes_layer"] = {
+            "workload": "oscillatory wave boundary layer: linearised model, no-slip bed, "
+                        "Nx=64 x Nz=33, depth 0.1 m, H=0.02 m, kh=0.6725, nu=1e-6, 40 steps "
+                        "per period, filters off, one tank, rtol 1e-10; closed_form_err = max "
+                        "|u - u_Stokes-layer| / U_0m within 6 delta_1 of the bed",
+            "fp64": run_stokes_layer("fp64"), "mixed": run_stokes_layer("mixed")}
+        print(f"# boundary layer: fp64 {out['stokes_layer']['fp64']['value']:.0f} solves/s, "
+              f"mixed {out['stokes_layer']['mixed']['value']:.0f} solves/s", file=sys.stderr,
+              flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wave)
     print(json.dumps(out))
