@@ -90,6 +90,10 @@ typedef struct {
                                domain (the plan's geometry is set with eta = 0) [0]          */
     int32_t no_slip;        /* rk4_stage bed: 1 = no-slip bed u = w = 0 (paper Sec. 5,
                                oscillatory wave boundary layer), see rk4_stage [0]           */
+    int32_t guess_steps;    /* rk4_stage initial guess: 0 = the solve starts from p as passed
+                               (the previous stage's pressure); m in 2..5 = from the
+                               extrapolation of the same stage's pressure over the previous m
+                               steps, see rk4_stage [0]                                     */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */
@@ -210,10 +214,23 @@ int poisson_solve(pmgw_plan plan, const double* b, double* p, double rtol, int32
  * included), and the viscous term is left out on the surface row, for which the paper gives no
  * stress condition (the surface row moves by the inviscid momentum equation). Pass a state whose
  * bed rows of u, w, Ku, Kw are zero.
+ * With opts.guess_steps = m >= 2 the plan records, at the start of each call, the pressure in p
+ * (the previous call's result) as that stage's value for the current step, and starts the solve
+ * from the polynomial extrapolation, in the step index, of stage k's pressure over its last
+ * c = min(m, recorded) steps: p0 = sum_{i=1..c} (-1)^(i+1) C(c, i) p_k[n - i] (degree c - 1
+ * through equally spaced steps). With c < 2 the solve starts from p as passed. The record
+ * restarts when a call's k does not follow the previous call's k cyclically (1..5, 1..) or
+ * dt changes, and on pmgw_history_reset. The stopping rule is unchanged: every solve still
+ * reaches rtol; only its starting point differs. Workspace: 5 m n2d doubles more.
  */
 int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, double* w,
               double* eta, double* Ku, double* Kw, double* Keta, double* p, double rtol,
               int32_t maxit, pmgw_info* info_dev);
+
+/* Forget the pressures recorded for opts.guess_steps (e.g. before stepping a new initial state
+ * with the same plan); the next rk4_stage calls start from p as passed until two steps are
+ * recorded again. No-op for plans without guess_steps. */
+int pmgw_history_reset(pmgw_plan plan);
 
 /*
  * out = A^T lambda for the operator of laplacian_apply (its exact transpose: D_x^T = -D_x,

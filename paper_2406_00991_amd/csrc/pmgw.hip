@@ -102,6 +102,13 @@ struct pmgw_plan_s {
   // constant image: [descs][jobs][per-tank tables...] copied at bind time
   std::vector<char> image;
   int64_t desc_off = 0, job_off = 0, info_off = 0, rk_off = 0, adj_off = 0;
+  // stage pressure history of opts.guess_steps: 5 rings of m slots of n2d doubles at hist_off;
+  // hist_cnt[s] recorded steps of stage s + 1, hist_head[s] its next slot, hist_k the last
+  // rk4_stage call's k (0: none), hist_dt its dt
+  int64_t hist_off = 0;
+  int hist_cnt[5] = {0, 0, 0, 0, 0}, hist_head[5] = {0, 0, 0, 0, 0};
+  int hist_k = 0;
+  double hist_dt = 0.0;
   // tanks grouped by finest-level row count (3, 5, 9, 17, 33): one solve launch per class
   int64_t ids_off[5] = {0, 0, 0, 0, 0};
   std::vector<int32_t> ids[5];
@@ -407,6 +414,8 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   if (o.bed_line != 0 && o.bed_line != 1) return fail(PMGW_EINVAL, "bed_line must be 0 or 1");
   if (o.linear != 0 && o.linear != 1) return fail(PMGW_EINVAL, "linear must be 0 or 1");
   if (o.no_slip != 0 && o.no_slip != 1) return fail(PMGW_EINVAL, "no_slip must be 0 or 1");
+  if (o.guess_steps != 0 && (o.guess_steps < 2 || o.guess_steps > 5))
+    return fail(PMGW_EINVAL, "guess_steps must be 0 or in 2..5");
   if (o.resident != 0 && o.resident != 1) return fail(PMGW_EINVAL, "resident must be 0 or 1");
   for (int t = 0; t < ntanks; ++t) {
     const int n = nx[t], M = nz[t] - 1;
@@ -569,6 +578,10 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   cur = align256(cur + rk_workspace_bytes(p->off2d[ntanks], p->off1d[ntanks]));
   p->adj_off = cur;
   cur = align256(cur + adj_workspace_bytes(p->off2d[ntanks], p->off1d[ntanks]));
+  if (o.guess_steps > 0) {
+    p->hist_off = cur;
+    cur = align256(cur + 8LL * 5 * o.guess_steps * p->off2d[ntanks]);
+  }
   p->total = cur;
 
   // block-inversion jobs
@@ -888,6 +901,47 @@ int launch_rk_all(pmgw_plan p, int which, const RkCoef& cf, double* u, double* w
 
 }  // namespace
 
+namespace {
+
+// The history step of rk4_stage with opts.guess_steps = m: record the incoming p as the value of
+// the previous call's stage, then extrapolate stage k's record into p (k_guess, one launch).
+int stage_guess(pmgw_plan p, int k, double dt, double* pr) {
+  const int m = p->opts.guess_steps;
+  const bool in_order = p->hist_k != 0 && k == p->hist_k % 5 + 1 && dt == p->hist_dt;
+  if (!in_order)
+    for (int s = 0; s < 5; ++s) p->hist_cnt[s] = p->hist_head[s] = 0;
+  GuessArgs g{};
+  g.store = -1;
+  if (in_order) {
+    const int s = p->hist_k - 1;
+    g.store = s * m + p->hist_head[s];
+    p->hist_head[s] = (p->hist_head[s] + 1) % m;
+    p->hist_cnt[s] = std::min(p->hist_cnt[s] + 1, m);
+  }
+  const int s = k - 1, c = p->hist_cnt[s];
+  if (c >= 2) {
+    g.nsrc = c;
+    double binom = 1.0;   // C(c, i), built up over i
+    for (int i = 1; i <= c; ++i) {
+      binom = binom * (c - i + 1) / i;
+      g.src[i - 1] = s * m + (p->hist_head[s] - i + m) % m;
+      g.c[i - 1] = (i % 2 == 1 ? 1.0 : -1.0) * binom;
+    }
+  }
+  p->hist_k = k;
+  p->hist_dt = dt;
+  if (g.store < 0 && g.nsrc == 0) return PMGW_OK;
+  const int64_t n2d = p->off2d[p->ntanks];
+  const int64_t blocks = std::min<int64_t>((n2d + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_guess, dim3((unsigned)blocks), dim3(256), 0, p->stream, pr,
+                     reinterpret_cast<double*>(p->ws + p->hist_off), n2d, g);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "initial-guess kernel launch");
+  return PMGW_OK;
+}
+
+}  // namespace
+
 extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, double* u, double* w,
                          double* eta, double* Ku, double* Kw, double* Keta, double* pr,
                          double rtol, int32_t maxit, pmgw_info* info_dev) {
@@ -917,11 +971,23 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   if (rc) return rc;
   rc = launch_rk_all(p, 1, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
   if (rc) return rc;
+  if (p->opts.guess_steps > 0) {
+    rc = stage_guess(p, k, dt, pr);
+    if (rc) return rc;
+  }
   pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev)
                                   : reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
   rc = launch_solve(p, MODE_SOLVE, rb.b, pr, rtol, maxit, dinfo);
   if (rc) return rc;
   return launch_rk_all(p, 2, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
+}
+
+extern "C" int pmgw_history_reset(pmgw_plan p) {
+  g_err.clear();
+  if (!p) return fail(PMGW_EINVAL, "plan is NULL");
+  for (int s = 0; s < 5; ++s) p->hist_cnt[s] = p->hist_head[s] = 0;
+  p->hist_k = 0;
+  return PMGW_OK;
 }
 
 namespace {

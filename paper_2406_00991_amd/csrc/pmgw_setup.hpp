@@ -1,5 +1,6 @@
 // Set-up kernels of the p-multigrid Poisson library, launched only by the host API: a fill
-// kernel, the geometry/metrics kernel and the block-inversion kernel.
+// kernel, the stage solve's initial-guess kernel, the geometry/metrics kernel and the
+// block-inversion kernels.
 #pragma once
 #include "pmgw_kernels.hpp"
 
@@ -10,6 +11,31 @@ __global__ void __launch_bounds__(256) k_fill(double* a, int64_t n, double v) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
     a[e] = v;
+}
+
+// Initial guess of a stage's pressure solve from the recorded history (opts.guess_steps):
+// store the incoming p (the previous stage's result) into slot `store` of the history, then
+// replace p by sum_i c_i H[src_i] (stage k's recorded steps). Elementwise over the n2d points
+// of every tank; the stored slot belongs to another stage than the sources.
+struct GuessArgs {
+  int store;      // history slot receiving p, or -1
+  int nsrc;       // number of source slots (0: p is left as is)
+  int src[5];
+  double c[5];
+};
+
+__global__ void __launch_bounds__(256) k_guess(double* p, double* hist, int64_t n2d,
+                                               GuessArgs g) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n2d;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = p[e];
+    if (g.store >= 0) hist[g.store * n2d + e] = v;
+    if (g.nsrc > 0) {
+      double s = 0.0;
+      for (int i = 0; i < g.nsrc; ++i) s += g.c[i] * hist[g.src[i] * n2d + e];
+      p[e] = s;
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------- geometry kernel

@@ -37,7 +37,8 @@ class Opts(ctypes.Structure):
                 ("cycle", ctypes.c_int32), ("coarse_exact", ctypes.c_int32),
                 ("resident", ctypes.c_int32), ("class_threads", ctypes.c_int32 * 5),
                 ("class_resident", ctypes.c_int32 * 5), ("bed_line", ctypes.c_int32),
-                ("linear", ctypes.c_int32), ("no_slip", ctypes.c_int32)]
+                ("linear", ctypes.c_int32), ("no_slip", ctypes.c_int32),
+                ("guess_steps", ctypes.c_int32)]
 
 # finest-level row counts of the per-class options (class_threads, class_resident)
 CLASS_ROWS = (3, 5, 9, 17, 33)
@@ -84,6 +85,7 @@ def lib():
         L.rk4_stage_adjoint.argtypes = ([_vp, ctypes.c_int32, ctypes.c_double] + [_vp] * 14 +
                                         [ctypes.c_double, ctypes.c_int32, _vp])
         L.pmgw_adjoint_vcycle.argtypes = [_vp, _vp, _vp]
+        L.pmgw_history_reset.argtypes = [_vp]
         L.pmgw_plan_destroy.argtypes = [_vp]
         L.pmgw_plan_destroy.restype = None
         L.pmgw_last_error.restype = ctypes.c_char_p
@@ -392,6 +394,11 @@ def rk4_step(plan, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10, maxit=100, inf
     """One full time step: stages 1..5 (stage 1 multiplies the registers K by zero)."""
     for k in range(1, 6):
         rk4_stage(plan, k, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol, maxit, info_dev)
+
+
+def history_reset(plan):
+    """Forget the stage pressures recorded for opts.guess_steps."""
+    _check(lib().pmgw_history_reset(plan._h))
 
 
 def profile_start(plan, capacity):

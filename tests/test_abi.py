@@ -52,7 +52,7 @@ def test_plan_rejects_bad_options_and_precision():
                 dict(nu1=-1), dict(threads=100), dict(threads=1024), dict(coarse_exact=2),
                 dict(class_threads={33: 96}), dict(class_threads=[0, 0, 0, 0, 1024]),
                 dict(class_resident={17: 3}), dict(class_resident={9: -1}), dict(bed_line=2),
-                dict(linear=2), dict(no_slip=-1)):
+                dict(linear=2), dict(no_slip=-1), dict(guess_steps=1), dict(guess_steps=6)):
         rc, _ = _create([32], [9], [1.0], opts=pmgw.default_opts(**bad))
         assert rc == pmgw.EINVAL, bad
 
