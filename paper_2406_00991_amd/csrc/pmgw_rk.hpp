@@ -1,17 +1,20 @@
 // Kernels of one low-storage Runge-Kutta stage with the pressure projection (paper Sec. 3.1-3.3,
-// Sec. 3.6), float64, one workgroup per tank, launched per finest-level row count NZ:
+// Sec. 3.6), float64, launched per finest-level row count NZ; one workgroup per tank, or per tank
+// and velocity component where the two components are independent (grid.y = 2):
 //
 //   k_rk_pre    surface: eta_t = -u~ D_x eta + w~; K_eta <- a K_eta + dt eta_t;
 //               eta <- filter_x(eta + b K_eta); the old surface is kept for the metrics.
 //   (geometry)  sigma-metrics of the old and new surface and the smoother blocks.
-//   k_rk_force  forcing at the old stage, F_u = -u D_x u - w_s D_s u - g D_x eta + nu Div Grad u,
-//               F_w = -u D_x w - w_s D_s w + nu Div Grad w with w_s = sigma_t + u sigma_x + w/d,
-//               sigma_t = -sigma eta_t / d; provisional u* = u + b (a K_u + dt F_u), w*; right-hand
-//               side rho/(b dt) Div^new(u*, w*) inside, 0 on the surface row and
+//   k_rk_force  per component: forcing at the old stage, F_u = -u D_x u - w_s D_s u - g D_x eta
+//               + nu Div Grad u, F_w = -u D_x w - w_s D_s w + nu Div Grad w with
+//               w_s = sigma_t + u sigma_x + w/d, sigma_t = -sigma eta_t / d; provisional
+//               u* = u + b (a K_u + dt F_u), w* likewise.
+//   k_rk_rhs    right-hand side rho/(b dt) Div^new(u*, w*) inside, 0 on the surface row and
 //               -rho/(b dt)(h_x u* + w*) on the bed row (eq. poissonp, eq. bcpd, eq. bcpdneu).
 //   (solve)     flexible GMRES / p-multigrid for the dynamic pressure p.
 //   k_rk_post   (G_x, G_z) = Grad^old p; K_u <- a K_u + dt (F_u - G_x/rho), K_w likewise;
-//               u <- filter(u + b K_u), w <- filter(w + b K_w) in x and sigma.
+//               r = (u + b K_u, w + b K_w).
+//   k_rk_filter per component: u <- filter(r_u), w <- filter(r_w) in x and sigma.
 //
 // Model options (RkCoef): lin = the linearised equations (eq. NSElin, eq. linFS): F without the
 // advection terms, eta_t = w~, and the host sets the geometry with eta = 0 (z1, zeroed by
@@ -59,6 +62,10 @@ inline RkBufs rk_bufs(char* base, int64_t n2d, int64_t n1d) {
   return r;
 }
 
+// Threads per stage workgroup (one workgroup per tank): eight wavefronts, so that the row
+// transforms of a 17-row tank (nine packed pairs) run about one pair per wavefront.
+constexpr int kStageThreads = 512;
+
 struct RkCoef {
   double a, b, dt, rho, g, nu;
   int lin = 0;     // linearised model: no advection, eta_t = w~, still-water sigma-map
@@ -93,7 +100,7 @@ __device__ __forceinline__ cpx<double> filt_mul(gptr<const double> fx, int N, in
 }
 
 template <int NZ>
-__global__ void __launch_bounds__(256) k_rk_pre(const TankDesc* __restrict__ descs,
+__global__ void __launch_bounds__(kStageThreads) k_rk_pre(const TankDesc* __restrict__ descs,
                                                 const int32_t* __restrict__ ids, char* ws,
                                                 RkCoef cf, const double* u, const double* w,
                                                 double* eta, double* Keta, RkBufs rb, int fftb) {
@@ -127,18 +134,26 @@ __global__ void __launch_bounds__(256) k_rk_pre(const TankDesc* __restrict__ des
                         [=](int, int i, double v) { e[i] = v; });
 }
 
+// Forcing and provisional velocity of one component per workgroup: blockIdx.y = 0 for u (level
+// temporaries t1..t3 of the finest level), 1 for w (r1, r2, b as temporaries: r1 and r2 are
+// written by k_rk_post later, b by k_rk_rhs after both components).
 template <int NZ>
-__global__ void __launch_bounds__(256) k_rk_force(const TankDesc* __restrict__ descs,
+__global__ void __launch_bounds__(kStageThreads) k_rk_force(const TankDesc* __restrict__ descs,
                                                   const int32_t* __restrict__ ids, char* ws,
                                                   RkCoef cf, const double* u, const double* w,
                                                   const double* Ku, const double* Kw, RkBufs rb,
                                                   int fftb) {
   const TankDesc& td = descs[ids[blockIdx.x]];
-  const int nx = td.nx, n = nx * NZ;
+  const int nx = td.nx, n = nx * NZ, comp = blockIdx.y;
   if (td.nz != NZ || nx < 8 || nx > 2048) return;
   Ctx<double> c;
   Lev<double> A;
   rk_ctx(ws, td, fftb, c, A);
+  if (comp == 1) {
+    A.t1 = as_global(rb.r1 + td.off2d);
+    A.t2 = as_global(rb.r2 + td.off2d);
+    A.t3 = as_global(rb.b + td.off2d);
+  }
   Ctx<double> cold = c;               // Div^old Grad^old for the viscous term
   cold.g.an = c.g.ao;
   cold.g.bn = c.g.bo;
@@ -146,34 +161,45 @@ __global__ void __launch_bounds__(256) k_rk_force(const TankDesc* __restrict__ d
   const Geo<double> g = c.g;
   const gptr<const double> sig = A.sig;
   const gptr<const double> uu = as_global(u + td.off2d), wwp = as_global(w + td.off2d);
-  const gptr<const double> ku = as_global(Ku + td.off2d), kw = as_global(Kw + td.off2d);
-  const gptr<double> Fu = as_global(rb.Fu + td.off2d), Fw = as_global(rb.Fw + td.off2d);
-  const gptr<double> us = as_global(rb.us + td.off2d), wsv = as_global(rb.ws + td.off2d);
-  const gptr<double> b = as_global(rb.b + td.off2d);
+  const gptr<const double> f = comp == 0 ? uu : wwp;
+  const gptr<const double> K = as_global((comp == 0 ? Ku : Kw) + td.off2d);
+  const gptr<double> F = as_global((comp == 0 ? rb.Fu : rb.Fw) + td.off2d);
+  const gptr<double> star = as_global((comp == 0 ? rb.us : rb.ws) + td.off2d);
   const gptr<const double> et = as_global(rb.etat + td.off1d);
   const gptr<const double> ex = as_global(rb.etax + td.off1d);
-  const gptr<double> t1 = A.t1, t2 = A.t2, t3 = A.t3;
-  const gptr<double> none(nullptr);
-  for (int comp = 0; comp < 2; ++comp) {
-    const gptr<const double> f = comp == 0 ? uu : wwp;
-    const gptr<double> F = comp == 0 ? Fu : Fw;
-    // F <- Div^old Grad^old f; leaves t1 = D_s f, t2 = D_x f
-    op_apply<double, NZ>(cold, A, FIN_FULL, f, F, gptr<const double>(nullptr), none, 0.0);
-    const gptr<const double> K = comp == 0 ? ku : kw;
-    const gptr<double> star = comp == 0 ? us : wsv;
-    for (int e = tid(); e < n; e += nthr()) {
-      const int j = e / nx, i = e - j * nx;
-      const double sx = g.ao[i] + g.bo[i] * sig[j];
-      const double wsig = -sig[j] * et[i] * g.ido[i] + uu[e] * sx + wwp[e] * g.ido[i];
-      double fo = (cf.noslip && j == 0) ? 0.0 : cf.nu * F[e];
-      if (!cf.lin) fo += -uu[e] * t2[e] - wsig * t1[e];
-      if (comp == 0) fo -= cf.g * ex[i];
-      F[e] = fo;
-      star[e] = f[e] + cf.b * (cf.a * K[e] + cf.dt * fo);
-    }
-    __syncthreads();
+  const gptr<double> t1 = A.t1, t2 = A.t2;
+  // F <- Div^old Grad^old f; leaves t1 = D_s f, t2 = D_x f
+  op_apply<double, NZ>(cold, A, FIN_FULL, f, F, gptr<const double>(nullptr),
+                       gptr<double>(nullptr), 0.0);
+  for (int e = tid(); e < n; e += nthr()) {
+    const int j = e / nx, i = e - j * nx;
+    const double sx = g.ao[i] + g.bo[i] * sig[j];
+    const double wsig = -sig[j] * et[i] * g.ido[i] + uu[e] * sx + wwp[e] * g.ido[i];
+    double fo = (cf.noslip && j == 0) ? 0.0 : cf.nu * F[e];
+    if (!cf.lin) fo += -uu[e] * t2[e] - wsig * t1[e];
+    if (comp == 0) fo -= cf.g * ex[i];
+    F[e] = fo;
+    star[e] = f[e] + cf.b * (cf.a * K[e] + cf.dt * fo);
   }
-  // right-hand side: scale * Div^new(u*, w*) with the boundary rows
+}
+
+// Right-hand side of the stage's pressure problem: scale Div^new(u*, w*) inside, 0 on the surface
+// row, -scale (h_x u* + w*) on the bed row.
+template <int NZ>
+__global__ void __launch_bounds__(kStageThreads) k_rk_rhs(const TankDesc* __restrict__ descs,
+                                                const int32_t* __restrict__ ids, char* ws,
+                                                RkCoef cf, RkBufs rb, int fftb) {
+  const TankDesc& td = descs[ids[blockIdx.x]];
+  const int nx = td.nx, n = nx * NZ;
+  if (td.nz != NZ || nx < 8 || nx > 2048) return;
+  Ctx<double> c;
+  Lev<double> A;
+  rk_ctx(ws, td, fftb, c, A);
+  const Geo<double> g = c.g;
+  const gptr<const double> sig = A.sig;
+  const gptr<const double> us = as_global(rb.us + td.off2d), wsv = as_global(rb.ws + td.off2d);
+  const gptr<double> b = as_global(rb.b + td.off2d);
+  const gptr<double> t1 = A.t1, t2 = A.t2, t3 = A.t3;
   col_dsig<double, NZ>(nx, A.Ds, us, t1);
   col_dsig<double, NZ>(nx, A.Ds, wsv, t3);
   __syncthreads();
@@ -190,8 +216,9 @@ __global__ void __launch_bounds__(256) k_rk_force(const TankDesc* __restrict__ d
   }
 }
 
+// Projection and velocity update: K <- a K + dt (F - Grad^old p / rho), r = (u, w) + b K.
 template <int NZ>
-__global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ descs,
+__global__ void __launch_bounds__(kStageThreads) k_rk_post(const TankDesc* __restrict__ descs,
                                                  const int32_t* __restrict__ ids, char* ws,
                                                  RkCoef cf, const double* p, double* u, double* w,
                                                  double* Ku, double* Kw, RkBufs rb, int fftb) {
@@ -204,13 +231,11 @@ __global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ de
   const Geo<double> g = c.g;
   const gptr<const double> sig = A.sig;
   const gptr<const double> pp = as_global(p + td.off2d);
-  const gptr<double> uu = as_global(u + td.off2d), wwp = as_global(w + td.off2d);
+  const gptr<const double> uu = as_global(u + td.off2d), wwp = as_global(w + td.off2d);
   const gptr<double> ku = as_global(Ku + td.off2d), kw = as_global(Kw + td.off2d);
   const gptr<const double> Fu = as_global(rb.Fu + td.off2d), Fw = as_global(rb.Fw + td.off2d);
   const gptr<double> r1 = as_global(rb.r1 + td.off2d), r2 = as_global(rb.r2 + td.off2d);
-  const gptr<double> t1 = A.t1, t2 = A.t2, t3 = A.t3;
-  const gptr<const double> fx = gcp<double>(ws, td.filtx);
-  const gptr<const double> fz = gcp<double>(ws, td.filtz);
+  const gptr<double> t1 = A.t1, t2 = A.t2;
   col_dsig<double, NZ>(nx, A.Ds, pp, t1);
   __syncthreads();
   dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb, [=](int j, int i) { return pp[j * nx + i]; },
@@ -228,20 +253,31 @@ __global__ void __launch_bounds__(256) k_rk_post(const TankDesc* __restrict__ de
     r1[e] = uu[e] + cf.b * a;
     r2[e] = wwp[e] + cf.b * bb;
   }
-  __syncthreads();
-  for (int comp = 0; comp < 2; ++comp) {
-    const gptr<const double> src = comp == 0 ? gptr<const double>(r1) : gptr<const double>(r2);
-    const gptr<double> dst = comp == 0 ? uu : wwp;
-    spectral_rows<double>(NZ, nx, c.log2nx, fftb,
-                          [=](int j, int i) { return src[j * nx + i]; },
-                          [=](int k, cpx<double> v) { return filt_mul(fx, nx, k, v); },
-                          [=](int j, int i, double v) { t3[j * nx + i] = v; });
-    col_dsig<double, NZ>(nx, fz, t3, dst);
+}
+
+// Filter of one updated component per workgroup (blockIdx.y = 0: u from r1 with t3 of the
+// finest level as temporary; 1: w from r2 with b, free after the solve), in x then sigma.
+template <int NZ>
+__global__ void __launch_bounds__(kStageThreads) k_rk_filter(const TankDesc* __restrict__ descs,
+                                                   const int32_t* __restrict__ ids, char* ws,
+                                                   RkCoef cf, double* u, double* w, RkBufs rb,
+                                                   int fftb) {
+  const TankDesc& td = descs[ids[blockIdx.x]];
+  const int nx = td.nx, comp = blockIdx.y;
+  if (td.nz != NZ || nx < 8 || nx > 2048) return;
+  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx, fftb);
+  const gptr<const double> src = as_global((comp == 0 ? rb.r1 : rb.r2) + td.off2d);
+  const gptr<double> dst = as_global((comp == 0 ? u : w) + td.off2d);
+  const gptr<double> t3 = comp == 0 ? gmp<double>(ws, td.a3) : as_global(rb.b + td.off2d);
+  const gptr<const double> fx = gcp<double>(ws, td.filtx);
+  const gptr<const double> fz = gcp<double>(ws, td.filtz);
+  spectral_rows<double>(NZ, nx, td.log2nx, fftb, [=](int j, int i) { return src[j * nx + i]; },
+                        [=](int k, cpx<double> v) { return filt_mul(fx, nx, k, v); },
+                        [=](int j, int i, double v) { t3[j * nx + i] = v; });
+  col_dsig<double, NZ>(nx, fz, t3, dst);
+  if (cf.noslip) {
     __syncthreads();
-    if (cf.noslip) {
-      for (int i = tid(); i < nx; i += nthr()) dst[(NZ - 1) * nx + i] = 0.0;
-      __syncthreads();
-    }
+    for (int i = tid(); i < nx; i += nthr()) dst[(NZ - 1) * nx + i] = 0.0;
   }
 }
 

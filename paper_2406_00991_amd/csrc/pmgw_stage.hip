@@ -12,15 +12,21 @@ namespace pmgw {
 #if PMGW_STAGE_PART == 0
 template <int NZ>
 void launch_k_rk(int which, unsigned grid, size_t lds, hipStream_t st, const RkArgs& a) {
-  if (which == 0)
-    hipLaunchKernelGGL(k_rk_pre<NZ>, dim3(grid), dim3(256), lds, st, a.descs, a.ids, a.ws, a.cf,
-                       a.u, a.w, a.eta, a.Keta, a.rb, a.fftb);
-  else if (which == 1)
-    hipLaunchKernelGGL(k_rk_force<NZ>, dim3(grid), dim3(256), lds, st, a.descs, a.ids, a.ws,
-                       a.cf, a.u, a.w, (const double*)a.Ku, (const double*)a.Kw, a.rb, a.fftb);
-  else
-    hipLaunchKernelGGL(k_rk_post<NZ>, dim3(grid), dim3(256), lds, st, a.descs, a.ids, a.ws, a.cf,
-                       a.pr, a.uo, a.wo, a.Ku, a.Kw, a.rb, a.fftb);
+  const dim3 blk(kStageThreads);
+  if (which == 0) {
+    hipLaunchKernelGGL(k_rk_pre<NZ>, dim3(grid), blk, lds, st, a.descs, a.ids, a.ws, a.cf, a.u,
+                       a.w, a.eta, a.Keta, a.rb, a.fftb);
+  } else if (which == 1) {
+    hipLaunchKernelGGL(k_rk_force<NZ>, dim3(grid, 2), blk, lds, st, a.descs, a.ids, a.ws, a.cf,
+                       a.u, a.w, (const double*)a.Ku, (const double*)a.Kw, a.rb, a.fftb);
+    hipLaunchKernelGGL(k_rk_rhs<NZ>, dim3(grid), blk, lds, st, a.descs, a.ids, a.ws, a.cf, a.rb,
+                       a.fftb);
+  } else {
+    hipLaunchKernelGGL(k_rk_post<NZ>, dim3(grid), blk, lds, st, a.descs, a.ids, a.ws, a.cf, a.pr,
+                       a.uo, a.wo, a.Ku, a.Kw, a.rb, a.fftb);
+    hipLaunchKernelGGL(k_rk_filter<NZ>, dim3(grid, 2), blk, lds, st, a.descs, a.ids, a.ws, a.cf,
+                       a.uo, a.wo, a.rb, a.fftb);
+  }
 }
 
 template void launch_k_rk<3>(int, unsigned, size_t, hipStream_t, const RkArgs&);
