@@ -515,6 +515,7 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
       LevelDesc& lv = d.lev[l];
       lv.nz = M + 1;
       lv.nzc = (M > 2) ? M / 2 + 1 : 0;
+      lv.dss = cur; cur = align256(cur + 16LL * lv.nz * lv.nz);
       for (int pr = 0; pr < 2; ++pr) {
         const int64_t w = pr == 0 ? 8 : 4;
         lv.ds[pr] = cur; cur = align256(cur + w * lv.nz * lv.nz);
@@ -624,6 +625,19 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
       put<float>(p->image, lv.ds[1], D);
       put<double>(p->image, lv.sig[0], s);
       put<float>(p->image, lv.sig[1], s);
+      const int nz = lv.nz;
+      std::vector<double> dss(2 * nz * nz, 0.0);
+      for (int j = 0; j < nz; ++j)
+        for (int c = 0; c < nz; ++c) {
+          double a = 0.0, b = 0.0;
+          for (int m = 0; m < nz; ++m) {
+            a += D[j * nz + m] * D[m * nz + c];
+            b += D[j * nz + m] * s[m] * D[m * nz + c];
+          }
+          dss[j * nz + c] = a;
+          dss[nz * nz + j * nz + c] = b;
+        }
+      put<double>(p->image, lv.dss, dss);
       if (lv.nzc) {
         const auto R = restriction(M);
         const auto P = prolongation(M);

@@ -22,6 +22,8 @@ struct LevelDesc {
   int32_t nz, nzc;                  // rows here, rows on the next coarser level (0 on coarsest)
   int64_t ds[2];                    // D_sigma [nz][nz], float64 / float32 copies
   int64_t sig[2];                   // sigma_j [nz]
+  int64_t dss;                      // D_s D_s and D_s diag(sigma) D_s, [2][nz][nz] float64
+                                    // (the column and mode blocks are combinations of these)
   int64_t R[2];                     // restriction [nzc][nz]
   int64_t P[2];                     // prolongation [nz][nzc]
   int64_t PT[2];                    // P^T [nzc][nz] (restriction of the transposed cycle)

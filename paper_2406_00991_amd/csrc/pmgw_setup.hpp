@@ -126,7 +126,6 @@ __global__ void __launch_bounds__(64) k_blocks(const TankDesc* __restrict__ desc
                                                const BlockJob* __restrict__ jobs, int njobs,
                                                char* ws) {
   __shared__ double A[kMaxNz][kMaxNz + 1];
-  __shared__ double Dsl[kMaxNz][kMaxNz + 1];
   __shared__ int piv[kMaxNz];
   const int64_t b = blockIdx.x;
   int lo = 0, hi = njobs - 1;
@@ -143,53 +142,43 @@ __global__ void __launch_bounds__(64) k_blocks(const TankDesc* __restrict__ desc
   const int t = tid();
   const double* Ds = cp<double>(ws, ld.ds[0]);
   const double* sig = cp<double>(ws, ld.sig[0]);
-  for (int e = t; e < nz * nz; e += 64) Dsl[e / nz][e % nz] = Ds[e];
-  __syncthreads();
+  // S2 = D_s D_s and SS = D_s diag(sigma) D_s: with sx = a + b sigma the interior rows are
+  // sum_m (D_s)_jm (D_s)_mc (sxn_j sxo_m + 1/(d_n d_o)) = (sxn_j a_o + 1/(d_n d_o)) S2_jc
+  // + sxn_j b_o SS_jc (plus c_xx on the diagonal of a column block)
+  const double* S2 = cp<double>(ws, ld.dss);
+  const double* SS = S2 + nz * nz;
   if (jb.kind == 0) {
     const double* G = cp<double>(ws, td.geo64);
     const int i = idx;
     const double ao = G[GEO_AO * nx + i], bo = G[GEO_BO * nx + i], ido = G[GEO_IDO * nx + i];
     const double an = G[GEO_AN * nx + i], bn = G[GEO_BN * nx + i], idn = G[GEO_IDN * nx + i];
     const double hx = G[GEO_HX * nx + i];
-    if (t < nz) {
-      const int j = t;
-      const double sxn = an + bn * sig[j];
-      const double bedc = -(hx * (ao + bo * sig[M]) + ido);
-      for (int c = 0; c < nz; ++c) {
-        double v;
-        if (j == 0) {
-          v = (c == 0) ? 1.0 : 0.0;
-        } else if (j == M) {
-          v = bedc * Dsl[M][c];
-        } else {
-          double s = 0.0;
-          for (int m = 0; m < nz; ++m)
-            s += Dsl[j][m] * Dsl[m][c] * (sxn * (ao + bo * sig[m]) + idn * ido);
-          v = s + ((c == j) ? td.cxx : 0.0);
-        }
-        A[j][c] = v;
+    const double bedc = -(hx * (ao + bo * sig[M]) + ido);
+    for (int e = t; e < nz * nz; e += 64) {
+      const int j = e / nz, c = e - j * nz;
+      double v;
+      if (j == 0) {
+        v = (c == 0) ? 1.0 : 0.0;
+      } else if (j == M) {
+        v = bedc * Ds[M * nz + c];
+      } else {
+        const double sxn = an + bn * sig[j];
+        v = (sxn * ao + idn * ido) * S2[e] + sxn * bo * SS[e] + ((c == j) ? td.cxx : 0.0);
       }
+      A[j][c] = v;
     }
   } else {
     const double* S = cp<double>(ws, td.scal);
     const double cbar = S[0], ebar = S[1];
     const int k = idx;
     const double kap = (k == nx / 2) ? 0.0 : td.kfac * (double)k;
-    if (t < nz) {
-      const int j = t;
-      for (int c = 0; c < nz; ++c) {
-        double v;
-        if (j == 0) {
-          v = (c == 0) ? 1.0 : 0.0;
-        } else if (j == M) {
-          v = -ebar * Dsl[M][c];
-        } else {
-          double s = 0.0;
-          for (int m = 0; m < nz; ++m) s += Dsl[j][m] * Dsl[m][c];
-          v = cbar * s - ((c == j) ? kap * kap : 0.0);
-        }
-        A[j][c] = v;
-      }
+    for (int e = t; e < nz * nz; e += 64) {
+      const int j = e / nz, c = e - j * nz;
+      double v;
+      if (j == 0) v = (c == 0) ? 1.0 : 0.0;
+      else if (j == M) v = -ebar * Ds[M * nz + c];
+      else v = cbar * S2[e] - ((c == j) ? kap * kap : 0.0);
+      A[j][c] = v;
     }
   }
   __syncthreads();
