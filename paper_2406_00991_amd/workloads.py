@@ -330,3 +330,93 @@ def stokes_layer(nx=64, nz=33, depth=0.1, H=0.02, kh=0.6725, nu=1e-6, steps_per_
     return dict(name="stokes_layer", nx=nx, nz=nz, L=L, h=np.full(nx, depth), u=u, w=w, eta=eta,
                 dt=T / steps_per_period, T=T, omega=om, k=k, delta1=d1, U0m=U0m, nu=nu,
                 zeta=zeta, exact=exact)
+
+
+def stream_function_wave(H, depth, period=None, length=None, N=24, current="euler", iters=40,
+                         tol=1e-13):
+    """Steady nonlinear wave of height H on depth h by the Fourier approximation method of
+    Rienecker and Fenton (1981), from either the period or the wavelength. current: "euler" =
+    Stokes' first definition of the wave speed (zero mean Eulerian current, c = ubar), "mass" =
+    the second (zero mean mass transport, c = Q / h, as in a closed flume).
+
+    In the frame moving with the wave (X = x - c t, zeta = z + h) the stream function is
+        psi = -ubar zeta + sum_{j=1..N} B_j sinh(j k zeta) / cosh(j k h) cos(j k X),
+    so the bed is the streamline psi = 0 and the relative velocities are U = psi_zeta,
+    W = -psi_X; at the N + 1 collocation points X_m = m L / (2N) on half a wavelength the surface
+    zeta = h + eta_m is the streamline psi = -Q and satisfies Bernoulli,
+    (U^2 + W^2) / 2 + g eta_m = R; the mean of eta is zero, eta_0 - eta_N = H, and k c T = 2 pi
+    (period given) or k = 2 pi / L (wavelength given). Newton's method on these 2N + 5 equations
+    from the linear wave. Earth-frame velocities: u = c + U, w = W. Returns k, c, ubar, Q, R,
+    B (j = 1..N), the surface cosine coefficients E (j = 0..N) and the collocation surface eta_m,
+    plus the largest residual.
+    """
+    g = G
+    h = float(depth)
+    if length is not None:
+        k0 = 2.0 * math.pi / length
+    else:
+        om = 2.0 * math.pi / period
+        k0 = om * om / g
+        for _ in range(200):                       # linear dispersion relation
+            k0 = k0 - (g * k0 * math.tanh(k0 * h) - om * om) / (
+                g * math.tanh(k0 * h) + g * k0 * h / math.cosh(k0 * h) ** 2)
+    c0 = math.sqrt(g / k0 * math.tanh(k0 * h))
+    m = np.arange(N + 1)
+    j = np.arange(1, N + 1)
+    # unknowns: [k, ubar, Q, R, B_1..B_N, eta_0..eta_N]
+    x = np.zeros(2 * N + 5)
+    x[0], x[1], x[2], x[3] = k0, c0, c0 * h, 0.5 * c0 * c0
+    x[4] = c0 * (H / 2.0) / math.tanh(k0 * h)
+    x[4 + N:] = (H / 2.0) * np.cos(math.pi * m / N)
+
+    def residual(x):
+        k, ub, Q, R = x[0], x[1], x[2], x[3]
+        B, eta = x[4:4 + N], x[4 + N:]
+        kX = np.outer(math.pi * m / N, j)          # j k X_m with X_m = m L / (2N)
+        zeta = h + eta
+        jkz = np.outer(zeta, j) * k
+        ch = np.cosh(j * k * h)
+        S = np.sinh(jkz) / ch
+        C = np.cosh(jkz) / ch
+        psi = -ub * zeta + (S * np.cos(kX)) @ B
+        U = -ub + (C * np.cos(kX)) @ (j * k * B)
+        W = (S * np.sin(kX)) @ (j * k * B)
+        f = np.empty_like(x)
+        f[:N + 1] = psi + Q
+        f[N + 1:2 * N + 2] = 0.5 * (U * U + W * W) + g * eta - R
+        wts = np.ones(N + 1)
+        wts[0] = wts[-1] = 0.5
+        f[2 * N + 2] = (wts @ eta) / N
+        f[2 * N + 3] = eta[0] - eta[-1] - H
+        cw = ub if current == "euler" else Q / h
+        f[2 * N + 4] = (k * cw * period - 2.0 * math.pi) if length is None else (k - k0)
+        return f
+
+    res = np.inf
+    for _ in range(iters):
+        f = residual(x)
+        res = float(np.abs(f).max())
+        if res < tol:
+            break
+        J = np.empty((x.size, x.size))
+        for q in range(x.size):
+            d = 1e-7 * max(1.0, abs(x[q]))
+            xp = x.copy()
+            xp[q] += d
+            xm = x.copy()
+            xm[q] -= d
+            J[:, q] = (residual(xp) - residual(xm)) / (2.0 * d)
+        x = x - np.linalg.solve(J, f)
+    k, ub, Q, R = x[0], x[1], x[2], x[3]
+    c = ub if current == "euler" else Q / h
+    B, eta = x[4:4 + N].copy(), x[4 + N:].copy()
+    # cosine coefficients of the surface through the N + 1 points (trapezoidal DCT-I)
+    wts = np.ones(N + 1)
+    wts[0] = wts[-1] = 0.5
+    E = np.array([(2.0 / N) * np.sum(wts * eta * np.cos(math.pi * q * m / N))
+                  for q in range(N + 1)])
+    E[0] *= 0.5
+    E[N] *= 0.5
+    return dict(k=float(k), c=float(c), ubar=float(ub), Q=float(Q), R=float(R), B=B, E=E,
+                eta_m=eta, H=H, depth=h, L=2.0 * math.pi / float(k),
+                T=2.0 * math.pi / (float(k) * float(c)), residual=res, N=N)
