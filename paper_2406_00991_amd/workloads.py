@@ -420,3 +420,84 @@ def stream_function_wave(H, depth, period=None, length=None, N=24, current="eule
     return dict(k=float(k), c=float(c), ubar=float(ub), Q=float(Q), R=float(R), B=B, E=E,
                 eta_m=eta, H=H, depth=h, L=2.0 * math.pi / float(k),
                 T=2.0 * math.pi / (float(k) * float(c)), residual=res, N=N)
+
+
+def smooth_ramp(chi):
+    """0 at chi <= 0, 1 at chi >= 1, chi^3 (10 - 15 chi + 6 chi^2) between (zero slope and
+    curvature at both ends)."""
+    c = np.clip(chi, 0.0, 1.0)
+    return c * c * c * (10.0 - 15.0 * c + 6.0 * c * c)
+
+
+def flume_zones(x, length, zone, ext=None):
+    """Relaxation strength r(x) and target window S(x) of a periodic flume (paper Sec. 5,
+    harmonic generation over a submerged bar: generation and absorption zones of one wavelength,
+    the generation zone carried on past the right end so that the periodic domain stays smooth).
+
+    - generation zone [0, zone): S = 1, r falls from 1 at x = 0 to 0 at x = zone;
+    - absorption zone [length - ext - zone, length - ext): S = 0 (still water), r rises 0 -> 1;
+    - extension [length - ext, length): r = 1, S rises 0 -> 1, meeting the generation zone's
+      fully relaxed end at the periodic seam (ext = zone / 2 unless given).
+    """
+    ext = 0.5 * zone if ext is None else ext
+    x = np.asarray(x, dtype=np.float64)
+    r = np.zeros_like(x)
+    S = np.zeros_like(x)
+    g = x < zone
+    r[g] = 1.0 - smooth_ramp(x[g] / zone)
+    S[g] = 1.0
+    a0 = length - ext - zone
+    a = (x >= a0) & (x < length - ext)
+    r[a] = smooth_ramp((x[a] - a0) / zone)
+    e = x >= length - ext
+    r[e] = 1.0
+    S[e] = smooth_ramp((x[e] - (length - ext)) / ext)
+    return r, S
+
+
+def stream_coef(sf, x0=0.0):
+    """Packed coefficients of a stream-function wave for the target evaluation:
+    [k, c, ubar, h0, x0, E_0..E_N, B_1..B_N] (crest at x = x0 + c t)."""
+    return np.concatenate([[sf["k"], sf["c"], sf["ubar"], sf["depth"], x0], sf["E"], sf["B"]])
+
+
+def flat_flume(nx=128, nz=17, waves=4, H=0.02, depth=0.4, period=2.02, steps_per_period=40):
+    """Periodic flat flume of `waves` wavelengths with zones of one wavelength (flume_zones),
+    still water at t = 0, incident stream-function wave (zero mass transport) ramped in over two
+    periods. Returns the tank dict of the stepping tests plus r, S, coef, T and dt."""
+    sf = stream_function_wave(H, depth, period=period, current="mass")
+    L = waves * sf["L"]
+    x, _ = nodes(nx, nz, L)
+    r, S = flume_zones(x, L, sf["L"])
+    z = np.zeros((nz, nx))
+    return dict(name="flat_flume", nx=nx, nz=nz, L=L, h=np.full(nx, depth), u=z, w=z.copy(),
+                eta=np.zeros(nx), r=r, S=S, coef=stream_coef(sf), nmodes=sf["N"], sf=sf,
+                T=period, dt=period / steps_per_period)
+
+
+def bar_flume(nx=1024, nz=33, H=0.02, period=2.02, steps_per_period=200):
+    """The submerged-bar flume (paper Sec. 5, harmonic generation over a submerged bar): depth
+    0.4 m, a 1:20 slope up to 0.1 m over 6 m, a 2 m crest, a 1:10 slope down over 3 m (corners
+    mollified as in ``bar``), in a periodic domain of ten incident wavelengths with the
+    generation zone at the left (the bar starts 6 m past it) and the absorption zone before the
+    right end (flume_zones); still water at t = 0 and the stream-function wave (H = 0.02 m,
+    T = 2.02 s, zero mass transport) ramped in over two periods."""
+    h0, sg = 0.4, 0.1
+    sf = stream_function_wave(H, h0, period=period, current="mass")
+    L = 10.0 * sf["L"]
+    x, _ = nodes(nx, nz, L)
+    x0 = sf["L"] + 6.0
+    br = np.array([x0, x0 + 6.0, x0 + 8.0, x0 + 11.0])
+    dm = np.array([-0.05, 0.05, 0.1, -0.1])
+    u = (x[None, :] - br[:, None]) / sg
+    h = h0 + np.sum(dm[:, None] * sg * (u * _Phi(u) + _phi(u)), axis=0)
+    r, S = flume_zones(x, L, sf["L"])
+    z = np.zeros((nz, nx))
+    return dict(name="bar_flume", nx=nx, nz=nz, L=L, h=h, u=z, w=z.copy(), eta=np.zeros(nx),
+                r=r, S=S, coef=stream_coef(sf), nmodes=sf["N"], sf=sf, T=period,
+                dt=period / steps_per_period)
+
+
+def ramp_in(t, T):
+    """Amplitude factor of the incident wave: smooth_ramp over the first two periods."""
+    return float(smooth_ramp(np.array(t / (2.0 * T))))
