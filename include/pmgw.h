@@ -227,6 +227,30 @@ int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, 
               double* eta, double* Ku, double* Kw, double* Keta, double* p, double rtol,
               int32_t maxit, pmgw_info* info_dev);
 
+/*
+ * Wave-flume relaxation zones (paper Sec. 5, harmonic generation over a submerged bar: waves
+ * generated and absorbed by relaxation toward a target in zones at the ends of the flume).
+ *
+ * pmgw_stream_target writes the target fields of every tank at time t: a steady
+ * stream-function wave (Fourier approximation) with coefficients coef (DEVICE array, per tank
+ * 2 nmodes + 6 doubles: k, c, ubar, h0, x0, E_0..E_nmodes, B_1..B_nmodes), scaled by a * S(x)
+ * (window S: device 1D field). With X = x - x0 - c t, s = a S:
+ *   eta_t = s sum_q E_q cos(q k X); on the target's sigma grid zeta_j = sigma_j (h0 + eta_t),
+ *   u_t = s ((c - ubar) + sum_q q k B_q cosh(q k zeta)/cosh(q k h0) cos(q k X)),
+ *   w_t = s sum_q q k B_q sinh(q k zeta)/cosh(q k h0) sin(q k X).
+ * nmodes in [1, 64]. Outputs are device fields (2D u_t, w_t, 1D eta_t).
+ *
+ * pmgw_relax blends the state toward the targets: q <- q + r (q_t - q) for u, w (every row) and
+ * eta, with the relaxation strength r per column (device 1D field, values in [0, 1]). Meant once
+ * per time step after the five rk4_stage calls (the next step's first stage multiplies the K
+ * registers by zero, so they need no blend). Both calls enqueue on the plan's stream and need a
+ * bound workspace.
+ */
+int pmgw_stream_target(pmgw_plan plan, const double* coef, int32_t nmodes, double t, double a,
+                       const double* window, double* u_t, double* w_t, double* eta_t);
+int pmgw_relax(pmgw_plan plan, const double* r, const double* u_t, const double* w_t,
+               const double* eta_t, double* u, double* w, double* eta);
+
 /* Forget the pressures recorded for opts.guess_steps (e.g. before stepping a new initial state
  * with the same plan); the next rk4_stage calls start from p as passed until two steps are
  * recorded again. No-op for plans without guess_steps. */

@@ -996,6 +996,39 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   return launch_rk_all(p, 2, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
 }
 
+extern "C" int pmgw_stream_target(pmgw_plan p, const double* coef, int32_t nmodes, double t,
+                                  double a, const double* window, double* u, double* w,
+                                  double* eta) {
+  g_err.clear();
+  const int rc = check_plan(p);
+  if (rc) return rc;
+  if (nmodes < 1 || nmodes > kStreamMaxModes)
+    return fail(PMGW_EINVAL, "nmodes must be in [1, 64]");
+  if (!coef || !window || !u || !w || !eta) return fail(PMGW_EINVAL, "arrays must be non-NULL");
+  if (!std::isfinite(t) || !std::isfinite(a)) return fail(PMGW_EINVAL, "t and a must be finite");
+  hipLaunchKernelGGL(k_stream_target, dim3((unsigned)p->ntanks, kMaxNz), dim3(256), 0, p->stream,
+                     reinterpret_cast<const TankDesc*>(p->ws + p->desc_off), p->ws, coef,
+                     (int)nmodes, t, a, window, u, w, eta);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "stream target kernel launch");
+  return PMGW_OK;
+}
+
+extern "C" int pmgw_relax(pmgw_plan p, const double* r, const double* u_t, const double* w_t,
+                          const double* eta_t, double* u, double* w, double* eta) {
+  g_err.clear();
+  const int rc = check_plan(p);
+  if (rc) return rc;
+  if (!r || !u_t || !w_t || !eta_t || !u || !w || !eta)
+    return fail(PMGW_EINVAL, "arrays must be non-NULL");
+  hipLaunchKernelGGL(k_relax, dim3((unsigned)p->ntanks, 16), dim3(256), 0, p->stream,
+                     reinterpret_cast<const TankDesc*>(p->ws + p->desc_off), r, u_t, w_t, eta_t,
+                     u, w, eta);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "relaxation kernel launch");
+  return PMGW_OK;
+}
+
 extern "C" int pmgw_history_reset(pmgw_plan p) {
   g_err.clear();
   if (!p) return fail(PMGW_EINVAL, "plan is NULL");

@@ -38,6 +38,78 @@ __global__ void __launch_bounds__(256) k_guess(double* p, double* hist, int64_t 
   }
 }
 
+// ----------------------------------------------------------------------------- relaxation zones
+//
+// Wave-flume relaxation (paper Sec. 5, harmonic generation over a submerged bar). The target of
+// tank t is a steady stream-function wave with coefficients coef + t (2 nm + 6) =
+// [k, c, ubar, h0, x0, E_0..E_nm, B_1..B_nm]: with X = x - x0 - c t and s = a S(x),
+// eta = s sum_q E_q cos(q k X) and, on the target's sigma grid zeta_j = sigma_j (h0 + eta),
+// u = s ((c - ubar) + sum_q q k B_q ch_q cos(q k X)), w = s sum_q q k B_q sh_q sin(q k X) with
+// ch_q, sh_q = exp(q k (zeta - h0)) (1 +- exp(-2 q k zeta)) / (1 + exp(-2 q k h0))
+// (= cosh(q k zeta) / cosh(q k h0) and sinh(q k zeta) / cosh(q k h0), without overflow).
+constexpr int kStreamMaxModes = 64;
+
+// One workgroup per (tank, row); row 0 also writes eta.
+__global__ void __launch_bounds__(256) k_stream_target(const TankDesc* __restrict__ descs,
+                                                       char* ws, const double* __restrict__ coef,
+                                                       int nm, double t, double a,
+                                                       const double* __restrict__ win, double* u,
+                                                       double* w, double* eta) {
+  const TankDesc& td = descs[blockIdx.x];
+  const int nx = td.nx, j = blockIdx.y;
+  if (j >= td.nz) return;
+  const double* cf = coef + (int64_t)blockIdx.x * (2 * nm + 6);
+  const double k = cf[0], c = cf[1], ub = cf[2], h0 = cf[3], x0 = cf[4];
+  const double* E = cf + 5;
+  const double* B = cf + 6 + nm;
+  const double sg = cp<double>(ws, td.lev[0].sig[0])[j];
+  const double dx = td.L / nx;
+  for (int i = tid(); i < nx; i += nthr()) {
+    const double X = i * dx - x0 - c * t;
+    const double s = a * win[td.off1d + i];
+    double e = 0.0;
+    for (int q = 0; q <= nm; ++q) e += E[q] * cos(q * k * X);
+    e *= s;
+    const double zeta = sg * (h0 + e);
+    double su = 0.0, sw = 0.0;
+    for (int q = 1; q <= nm; ++q) {
+      const double kq = q * k;
+      const double up = exp(kq * (zeta - h0)), em = exp(-2.0 * kq * zeta);
+      const double den = 1.0 + exp(-2.0 * kq * h0);
+      double sn, cs;
+      sincos(kq * X, &sn, &cs);
+      su += kq * B[q - 1] * (up * (1.0 + em) / den) * cs;
+      sw += kq * B[q - 1] * (up * (1.0 - em) / den) * sn;
+    }
+    const int64_t o = td.off2d + (int64_t)j * nx + i;
+    u[o] = s * ((c - ub) + su);
+    w[o] = s * sw;
+    if (j == 0) eta[td.off1d + i] = e;
+  }
+}
+
+// q <- q + r (q_target - q) for u, w (every row) and eta, r per column; grid (tanks, chunks).
+__global__ void __launch_bounds__(256) k_relax(const TankDesc* __restrict__ descs,
+                                               const double* __restrict__ r,
+                                               const double* __restrict__ ut,
+                                               const double* __restrict__ wt,
+                                               const double* __restrict__ et, double* u,
+                                               double* w, double* eta) {
+  const TankDesc& td = descs[blockIdx.x];
+  const int nx = td.nx, n = nx * td.nz;
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < n; e += gridDim.y * blockDim.x) {
+    const int i = e % nx;
+    const double rr = r[td.off1d + i];
+    const int64_t o = td.off2d + e;
+    u[o] = u[o] + rr * (ut[o] - u[o]);
+    w[o] = w[o] + rr * (wt[o] - w[o]);
+    if (e < nx) {
+      const int64_t o1 = td.off1d + e;
+      eta[o1] = eta[o1] + rr * (et[o1] - eta[o1]);
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------- geometry kernel
 
 constexpr int kGeoFftBytes = 32768;   // the geometry kernel: 2 x 32 KB of FFT LDS + twiddles

@@ -86,6 +86,9 @@ def lib():
                                         [ctypes.c_double, ctypes.c_int32, _vp])
         L.pmgw_adjoint_vcycle.argtypes = [_vp, _vp, _vp]
         L.pmgw_history_reset.argtypes = [_vp]
+        L.pmgw_stream_target.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.pmgw_relax.argtypes = [_vp] + [_vp] * 7
         L.pmgw_plan_destroy.argtypes = [_vp]
         L.pmgw_plan_destroy.restype = None
         L.pmgw_last_error.restype = ctypes.c_char_p
@@ -394,6 +397,24 @@ def rk4_step(plan, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10, maxit=100, inf
     """One full time step: stages 1..5 (stage 1 multiplies the registers K by zero)."""
     for k in range(1, 6):
         rk4_stage(plan, k, dt, h, u, w, eta, Ku, Kw, Keta, p, rtol, maxit, info_dev)
+
+
+def stream_target(plan, coef, nmodes, t, a, window, u_t, w_t, eta_t):
+    """Relaxation targets at time t: the stream-function wave of coefficients coef (device
+    float64, ntanks x (2 nmodes + 6)) times a * window, into u_t, w_t (2D) and eta_t (1D)."""
+    import torch
+    (cp,) = _ptrs([(coef, torch.float64, plan.ntanks * (2 * int(nmodes) + 6))],
+                  plan.device_index)
+    args = _fields(plan, (window, 1), (u_t, 2), (w_t, 2), (eta_t, 1))
+    _check(lib().pmgw_stream_target(plan._h, cp, int(nmodes), float(t), float(a), *args))
+    _trace("stream_target")
+
+
+def relax(plan, r, u_t, w_t, eta_t, u, w, eta):
+    """q <- q + r (q_t - q) for u, w and eta (r per column)."""
+    _check(lib().pmgw_relax(plan._h, *_fields(plan, (r, 1), (u_t, 2), (w_t, 2), (eta_t, 1),
+                                              (u, 2), (w, 2), (eta, 1))))
+    _trace("relax")
 
 
 def history_reset(plan):
