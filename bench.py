@@ -334,6 +334,52 @@ def run_stokes_layer(precision, warmup=2, rtol=1e-10):
             "closed_form_err": float(np.abs(u[near] - ue[near]).max() / t["U0m"])}
 
 
+def run_bar_flume(steps=12, warmup=2, rtol=1e-10, guess=4):
+    """The submerged-bar flume (1024 x 33, float64: on this bed the float32 cycle is near its
+    stability edge; zones of one wavelength, stream-function wave
+    H = 0.02 m, T = 2.02 s ramped in from still water, as the experiment starts): `steps` RK4
+    steps after `warmup`, each followed by the target evaluation and the relaxation; solves/s
+    over the whole stepping. These first steps have near-zero right-hand sides and take about
+    twice the FGMRES iterations of the developed flow."""
+    import torch
+
+    from paper_2406_00991_amd import pmgw
+    from paper_2406_00991_amd import workloads as wl
+    fl = wl.bar_flume()
+    T = Tank(fl, "fp64", 5 * (steps + warmup), pmgw.default_opts(guess_steps=guess))
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64,
+                                 device="cuda")
+    r, S, coef = dev(fl["r"]), dev(fl["S"]), dev(fl["coef"])
+    ut, wt, et = T.plan.field(), T.plan.field(), torch.zeros_like(T.eta)
+    mass0 = float(T.eta.sum())
+
+    def step(n):
+        T.step(fl["dt"], rtol)
+        t = (n + 1) * fl["dt"]
+        pmgw.stream_target(T.plan, coef, fl["nmodes"], t, wl.ramp_in(t, fl["T"]), S, ut, wt, et)
+        pmgw.relax(T.plan, r, ut, wt, et, T.u, T.w, T.eta)
+
+    for n in range(warmup):
+        step(n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(warmup, warmup + steps):
+        step(n)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    infos = T.infos(5 * warmup, 5 * steps)
+    return {"workload": "submerged-bar flume, Nx=1024 x Nz=33, L = 10 incident wavelengths "
+                        "(37.4 m), depth 0.4 m to 0.1 m over the bar, generation and absorption "
+                        "zones of one wavelength, stream-function wave H=0.02 m, T=2.02 s "
+                        "ramped in over two periods from still water, float64, rtol 1e-10, steps "
+                        f"{warmup + 1}..{warmup + steps} from rest, relaxation after each step",
+            "value": 5 * steps / wall, "unit": "solves/s", "ms_per_step": 1e3 * wall / steps,
+            "mean_iters": float(np.mean([i["iters"] for i in infos])),
+            "max_iters": int(max(i["iters"] for i in infos)),
+            "status": sorted({i["status"] for i in infos}),
+            "mean_eta_change": (float(T.eta.sum()) - mass0) / fl["nx"]}
+
+
 # ----------------------------------------------------------------------------- oracle timing
 def _cores():
     try:
@@ -428,6 +474,8 @@ def main():
                     help="opts.guess_steps of the stepping plans: each stage's solve starts from "
                          "that stage's pressure extrapolated over this many previous steps "
                          "(0: from the previous stage's pressure)")
+    ap.add_argument("--no-flume", action="store_true",
+                    help="skip the submerged-bar flume stepping reported beside the headline")
     ap.add_argument("--no-layer", action="store_true",
                     help="skip the oscillatory boundary-layer stepping reported beside the "
                          "headline")
@@ -549,6 +597,10 @@ def main():
             "fp64": run_stokes_layer("fp64"), "mixed": run_stokes_layer("mixed")}
         print(f"# boundary layer: fp64 {out['stokes_layer']['fp64']['value']:.0f} solves/s, "
               f"mixed {out['stokes_layer']['mixed']['value']:.0f} solves/s", file=sys.stderr,
+              flush=True)
+    if not args.no_flume:
+        out["bar_flume"] = run_bar_flume()
+        print(f"# bar flume: {out['bar_flume']['value']:.1f} solves/s", file=sys.stderr,
               flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wave)
