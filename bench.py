@@ -474,6 +474,9 @@ def main():
                     help="opts.guess_steps of the stepping plans: each stage's solve starts from "
                          "that stage's pressure extrapolated over this many previous steps "
                          "(0: from the previous stage's pressure)")
+    ap.add_argument("--no-prev", action="store_true",
+                    help="skip the stepping with each solve started from the previous stage's "
+                         "pressure (reported beside the headline)")
     ap.add_argument("--no-flume", action="store_true",
                     help="skip the submerged-bar flume stepping reported beside the headline")
     ap.add_argument("--no-layer", action="store_true",
@@ -511,7 +514,7 @@ def main():
         res["fp64"] = run_precision(wave, "fp64", args.steps, args.warmup, rtol, gs)
         print(f"# fp64: {args.steps} steps in {res['fp64']['wall']:.3f} s", file=sys.stderr,
               flush=True)
-    if gs:
+    if gs and not args.no_prev:
         res["mixed_prev"] = run_precision(wave, "mixed", args.steps, args.warmup, rtol, 0)
         print(f"# mixed, previous-stage start: {args.steps} steps in "
               f"{res['mixed_prev']['wall']:.3f} s", file=sys.stderr, flush=True)

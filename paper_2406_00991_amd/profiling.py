@@ -88,6 +88,7 @@ def main():
     a = sub.add_parser("stats")
     a.add_argument("csv")
     a.add_argument("--command", required=True)
+    a.add_argument("--top", type=int, default=12, help="rows of the table (kernels by total time)")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -96,7 +97,7 @@ def main():
     b.add_argument("--source-sha256", required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
-        sys.stdout.write(stats(args.csv, args.command))
+        sys.stdout.write(stats(args.csv, args.command, args.top))
     else:
         json.dump(traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.command,
                           args.source_sha256), sys.stdout, indent=1)
