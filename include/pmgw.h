@@ -221,7 +221,9 @@ int poisson_solve(pmgw_plan plan, const double* b, double* p, double rtol, int32
  * through equally spaced steps). With c < 2 the solve starts from p as passed. The record
  * restarts when a call's k does not follow the previous call's k cyclically (1..5, 1..) or
  * dt changes, and on pmgw_history_reset. The stopping rule is unchanged: every solve still
- * reaches rtol; only its starting point differs. Workspace: 5 m n2d doubles more.
+ * reaches rtol; only its starting point differs. Workspace: 5 m n2d doubles more. The record's
+ * slots are chosen on the host at each call, so a stage captured into a HIP graph replays the
+ * slots of its capture: capture stages only of plans without guess_steps.
  */
 int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, double* w,
               double* eta, double* Ku, double* Kw, double* Keta, double* p, double rtol,
