@@ -72,8 +72,8 @@ int check3(pmgw3_plan p) {
 int launch3(pmgw3_plan p, int mode, const double* in, double* out, double rtol, int maxit,
             Info3* info) {
   const Tank3* d = reinterpret_cast<const Tank3*>(p->ws + p->desc_off);
-  hipLaunchKernelGGL(k3_solve, dim3(p->ntanks), dim3(256), kLds3, p->stream, d, p->ws, mode, in,
-                     out, rtol, maxit, info, opts3(p->opts));
+  hipLaunchKernelGGL(k3_solve, dim3(p->ntanks), dim3(kThreads3), kLds3, p->stream, d, p->ws,
+                     mode, in, out, rtol, maxit, info, opts3(p->opts));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail3(e, "3D solve kernel launch");
   return PMGW_OK;

@@ -465,7 +465,10 @@ struct Kry3 {
   double res;
 };
 
-__global__ void __launch_bounds__(256) k3_solve(const Tank3* __restrict__ descs, char* ws,
+// Threads per 3D solve workgroup (one workgroup per tank): eight wavefronts.
+constexpr int kThreads3 = 1024;
+
+__global__ void __launch_bounds__(kThreads3) k3_solve(const Tank3* __restrict__ descs, char* ws,
                                                 int mode, const double* in, double* out,
                                                 double rtol, int maxit, Info3* info, Opts3 o) {
   __shared__ Kry3 K;
