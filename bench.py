@@ -86,11 +86,12 @@ def solve_bytes(nx, nz, iters, ws):
 
 
 def kernel_source_hash():
-    """Hash of the HIP sources; the stored HBM counter readings are used only while it matches."""
+    """Hash of the 2D library's HIP sources (every file but the 3D tanks' pmgw3d*); the stored
+    HBM counter readings of the 2D solve kernel are used only while it matches."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2406_00991_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp")):
+        if name.endswith((".hip", ".hpp")) and not name.startswith("pmgw3d"):
             with open(os.path.join(d, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
