@@ -75,6 +75,7 @@ def run(plan, h, st, dt, nsteps, rtol=1e-12, checkpoint=None):
     cps = []
     seg = checkpoint or nsteps
     infos = _Infos(plan, 5 * max(1, min(seg, nsteps)), 1)
+    pmgw.history_reset(plan)        # a plan with guess_steps starts its pressure record afresh
     for n in range(nsteps):
         if checkpoint and n % checkpoint == 0:
             infos.check("forward stepping")
@@ -104,6 +105,7 @@ def gradient(plan, h, st0, dt, nsteps, bar_final, checkpoint=10, rtol=1e-12):
         last = min(nsteps, first + checkpoint)
         cur = _clone(cps[c])
         inputs = []
+        pmgw.history_reset(plan)    # the recompute jumps back in time: no stale pressure record
         for _ in range(first, last):
             for k in range(1, 6):
                 inputs.append((k, _clone(cur)))

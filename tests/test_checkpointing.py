@@ -2,8 +2,9 @@
 
 The library calls are replaced by the oracle's forward stage and reverse stage on CPU tensors, so
 that only the ordering of the sweep is under test: checkpoints every C steps (C dividing the step
-count or not), recomputation of each segment's stage inputs, and the reverse order of the stage
-adjoints. The result must equal the oracle's gradient taken without checkpoints.
+count or not), recomputation of each segment's stage inputs, the reverse order of the stage
+adjoints, and a restart of the stage-pressure record (opts.guess_steps) before every sweep that
+jumps back in time. The result must equal the oracle's gradient taken without checkpoints.
 """
 import types
 
@@ -54,6 +55,9 @@ class FakeLib:
             t.copy_(torch.from_numpy(np.ascontiguousarray(a).ravel()))
         self.calls.append(("f", k))
 
+    def history_reset(self, plan):
+        self.calls.append(("reset", None))
+
     def rk4_stage_adjoint(self, plan, k, dt, h, st, bar, hbar, rtol=0, maxit=0, info_dev=None):
         self._record("r", info_dev, 2)
         s = self._state(*(st[q] for q in ("u", "w", "eta", "Ku", "Kw", "Keta", "p")))
@@ -73,6 +77,7 @@ PLAN = types.SimpleNamespace(ntanks=1, device="cpu")
 def _patch(monkeypatch, fake):
     ns = types.SimpleNamespace(
         rk4_stage=fake.rk4_stage, rk4_stage_adjoint=fake.rk4_stage_adjoint,
+        history_reset=fake.history_reset,
         info_buffer=lambda n, device=None: torch.zeros(2 * n, dtype=torch.float64),
         read_info=pmgw.read_info, OK=pmgw.OK, PmgwError=pmgw.PmgwError)
     monkeypatch.setattr(ag, "pmgw", ns)
@@ -115,3 +120,9 @@ def test_checkpointed_sweep_equals_plain_gradient(monkeypatch, checkpoint):
     assert rev == [5, 4, 3, 2, 1] * nsteps
     fwd = sum(1 for kind, _ in fake.calls if kind == "f")
     assert fwd == 2 * 5 * nsteps          # the checkpointed run plus one recompute per segment
+    # the stage-pressure record restarts before the forward run and before every recompute
+    # (the recompute jumps back in time); each reset is followed by a stage-1 forward call
+    kinds = [kind for kind, _ in fake.calls]
+    resets = [i for i, kind in enumerate(kinds) if kind == "reset"]
+    assert len(resets) == 1 + -(-nsteps // checkpoint)
+    assert all(fake.calls[i + 1] == ("f", 1) for i in resets)
