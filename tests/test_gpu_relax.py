@@ -142,3 +142,48 @@ def test_flume_generates_the_incident_wave():
             errs.append(np.abs(eta.cpu().numpy()[inner] - ei[inner]).max() / (fl["sf"]["H"] / 2))
     assert max(errs) <= 0.05, errs
     assert errs[-1] <= 1.05 * errs[2], errs
+
+
+def test_bar_flume_full_size_properties():
+    """The submerged-bar flume at the size and precision the benchmark times (1024 x 33, float64,
+    guess_steps 4): over three steps from rest (incident wave at full amplitude from t0 = two
+    periods) every stage solve converges to 1e-10, and the blend sets the state to the target
+    (to rounding) where r = 1 and leaves it bit for bit where r = 0 (properties of any size;
+    the blend itself is compared with the oracle element by element at the smaller sizes
+    above)."""
+    from paper_2406_00991_amd import pmgw
+    fl = wl.bar_flume()
+    nx, nz = fl["nx"], fl["nz"]
+    plan = pmgw.Plan([nx], [nz], [fl["L"]], precision="fp64",
+                     opts=pmgw.default_opts(guess_steps=4))
+    u, w, eta, h = dev(fl["u"]), dev(fl["w"]), dev(fl["eta"]), dev(fl["h"])
+    Ku, Kw, Keta, p = (dev(np.zeros(plan.n2d)), dev(np.zeros(plan.n2d)), dev(np.zeros(nx)),
+                       dev(np.zeros(plan.n2d)))
+    r, S, coef = dev(fl["r"]), dev(fl["S"]), dev(fl["coef"])
+    ut, wt, et = plan.field(), plan.field(), dev(np.zeros(nx))
+    info = pmgw.info_buffer(1)
+    t0 = 2 * fl["T"]
+    full, free = fl["r"] == 1.0, fl["r"] == 0.0
+    assert full.sum() > 10 and free.sum() > 10
+    for n in range(3):
+        for k in range(1, 6):
+            pmgw.rk4_stage(plan, k, fl["dt"], h, u, w, eta, Ku, Kw, Keta, p, rtol=1e-10,
+                           maxit=200, info_dev=info)
+            rec = pmgw.read_info(info)[0]
+            assert rec["status"] == 0 and rec["relres"] <= 1e-10
+        un, wn, en = (a.cpu().numpy() for a in (u, w, eta))
+        un, wn = un.reshape(nz, nx), wn.reshape(nz, nx)
+        t = t0 + (n + 1) * fl["dt"]
+        pmgw.stream_target(plan, coef, fl["nmodes"], t, 1.0, S, ut, wt, et)
+        pmgw.relax(plan, r, ut, wt, et, u, w, eta)
+        ua, wa, ea = (a.cpu().numpy() for a in (u, w, eta))
+        ua, wa = ua.reshape(nz, nx), wa.reshape(nz, nx)
+        tu, tw = ut.cpu().numpy().reshape(nz, nx), wt.cpu().numpy().reshape(nz, nx)
+        te = et.cpu().numpy()
+        # r = 1: q + (q_t - q) is q_t to the rounding of one subtraction and one addition
+        ulp = lambda a, b: 4 * np.finfo(np.float64).eps * (np.abs(a) + np.abs(b))
+        assert np.all(np.abs(ua[:, full] - tu[:, full]) <= ulp(un[:, full], tu[:, full]))
+        assert np.all(np.abs(wa[:, full] - tw[:, full]) <= ulp(wn[:, full], tw[:, full]))
+        assert np.all(np.abs(ea[full] - te[full]) <= ulp(en[full], te[full]))
+        assert np.array_equal(ua[:, free], un[:, free]) and np.array_equal(ea[free], en[free])
+        assert np.array_equal(wa[:, free], wn[:, free])
