@@ -137,6 +137,11 @@ struct pmgw_plan_s {
   // forked from and joined back to `stream`; created on first use
   hipStream_t side[15] = {};
   hipEvent_t fork = nullptr, join[15] = {};
+  // rk4_stage runs the smoother set-up (block inverses, optional bed-line and coarse set-ups) on
+  // this stream, forked after the geometry kernel and joined before the solve, so that it
+  // overlaps the forcing kernels; created on first use, default priority
+  hipStream_t setup_side = nullptr;
+  hipEvent_t setup_fork = nullptr, setup_join = nullptr;
   int nclasses = 0;
   ~pmgw_plan_s() {
     for (hipEvent_t e : ev0) (void)hipEventDestroy(e);
@@ -146,6 +151,9 @@ struct pmgw_plan_s {
       if (join[g]) (void)hipEventDestroy(join[g]);
     }
     if (fork) (void)hipEventDestroy(fork);
+    if (setup_fork) (void)hipEventDestroy(setup_fork);
+    if (setup_join) (void)hipEventDestroy(setup_join);
+    if (setup_side) (void)hipStreamDestroy(setup_side);
   }
 };
 
@@ -251,6 +259,16 @@ void launch_group(pmgw_plan p, int g, int mode, const double* in, double* out, d
     launch_k_solve_wide<TV, NZ>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
   else
     launch_k_solve<TV, NZ, TR>(v.count, thr, lds_bytes(a.fftb, v.maxnx), st, a);
+}
+
+// Creates the set-up stream of rk4_stage and its fork/join events once.
+int ensure_setup_stream(pmgw_plan p) {
+  if (p->setup_side) return PMGW_OK;
+  hipError_t e = hipEventCreateWithFlags(&p->setup_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->setup_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->setup_side, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "creating the set-up stream");
+  return PMGW_OK;
 }
 
 // Creates the side streams and fork/join events once (only plans with several launch groups).
@@ -696,37 +714,60 @@ int pmgw_field_offsets(pmgw_plan p, int64_t* off2d, int64_t* off1d) {
   return PMGW_OK;
 }
 
-int pmgw_set_geometry(pmgw_plan p, const double* h, const double* eo, const double* en) {
-  g_err.clear();
-  int rc = check_plan(p);
-  if (rc) return rc;
-  if (!h || !eo || !en) return fail(PMGW_EINVAL, "h, eta_old and eta_new must be non-NULL");
+}  // extern "C"
+
+namespace {
+
+// sigma-metrics of both geometries (k_geometry) on stream st.
+int geometry_kernel(pmgw_plan p, const double* h, const double* eo, const double* en,
+                    hipStream_t st) {
+  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  hipLaunchKernelGGL(k_geometry, dim3(p->ntanks), dim3(256), lds_bytes(kGeoFftBytes, p->maxnx_all),
+                     st, d, p->ws, h, eo, en);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
+  return PMGW_OK;
+}
+
+// The smoother's set-up from the metrics: block inverses, and the bed-line and direct coarse
+// solve set-ups when enabled, on stream st.
+int setup_kernels(pmgw_plan p, hipStream_t st) {
   const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
   const BlockJob* j = reinterpret_cast<const BlockJob*>(p->ws + p->job_off);
-  hipLaunchKernelGGL(k_geometry, dim3(p->ntanks), dim3(256), lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream,
-                     d, p->ws, h, eo, en);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
   if (p->prec == PMGW_FP64)
-    hipLaunchKernelGGL(k_blocks<double>, dim3((unsigned)p->nblocks), dim3(64), 0, p->stream, d, j,
+    hipLaunchKernelGGL(k_blocks<double>, dim3((unsigned)p->nblocks), dim3(64), 0, st, d, j,
                        (int)p->jobs.size(), p->ws);
   else
-    hipLaunchKernelGGL(k_blocks<float>, dim3((unsigned)p->nblocks), dim3(64), 0, p->stream, d, j,
+    hipLaunchKernelGGL(k_blocks<float>, dim3((unsigned)p->nblocks), dim3(64), 0, st, d, j,
                        (int)p->jobs.size(), p->ws);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "block kernel launch");
   if (p->opts.bed_line) {
     hipLaunchKernelGGL(k_bedline_setup, dim3(p->ntanks, kMaxLev), dim3(kBedLineThreads),
-                       lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream, d, p->ws);
+                       lds_bytes(kGeoFftBytes, p->maxnx_all), st, d, p->ws);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "bed-line set-up kernel launch");
   }
   if (p->opts.coarse_exact) {
     hipLaunchKernelGGL(k_coarse_setup, dim3(p->ntanks), dim3(kCoarseThreads),
-                       lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream, d, p->ws);
+                       lds_bytes(kGeoFftBytes, p->maxnx_all), st, d, p->ws);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "coarse set-up kernel launch");
   }
+  return PMGW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pmgw_set_geometry(pmgw_plan p, const double* h, const double* eo, const double* en) {
+  g_err.clear();
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!h || !eo || !en) return fail(PMGW_EINVAL, "h, eta_old and eta_new must be non-NULL");
+  if ((rc = geometry_kernel(p, h, eo, en, p->stream))) return rc;
+  if ((rc = setup_kernels(p, p->stream))) return rc;
   p->geometry_set = true;
   return PMGW_OK;
 }
@@ -981,14 +1022,27 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   rc = launch_rk_all(p, 0, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
   if (rc) return rc;
   // the linearised model keeps the still-water geometry: k_rk_pre leaves rb.z1 at zero
-  rc = cf.lin ? pmgw_set_geometry(p, h, rb.z1, rb.z1) : pmgw_set_geometry(p, h, rb.eo, eta);
+  rc = cf.lin ? geometry_kernel(p, h, rb.z1, rb.z1, p->stream)
+              : geometry_kernel(p, h, rb.eo, eta, p->stream);
   if (rc) return rc;
+  // the smoother set-up needs only the metrics: it runs on the set-up stream while the forcing
+  // and right-hand-side kernels run here, and is joined before the solve
+  if ((rc = ensure_setup_stream(p))) return rc;
+  hipError_t e = hipEventRecord(p->setup_fork, p->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->setup_side, p->setup_fork, 0);
+  if (e != hipSuccess) return hip_fail(e, "set-up fork");
+  if ((rc = setup_kernels(p, p->setup_side))) return rc;
+  e = hipEventRecord(p->setup_join, p->setup_side);
+  if (e != hipSuccess) return hip_fail(e, "set-up join");
+  p->geometry_set = true;
   rc = launch_rk_all(p, 1, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
   if (rc) return rc;
   if (p->opts.guess_steps > 0) {
     rc = stage_guess(p, k, dt, pr);
     if (rc) return rc;
   }
+  e = hipStreamWaitEvent(p->stream, p->setup_join, 0);
+  if (e != hipSuccess) return hip_fail(e, "set-up join");
   pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev)
                                   : reinterpret_cast<pmgw_info_dev*>(p->ws + p->info_off);
   rc = launch_solve(p, MODE_SOLVE, rb.b, pr, rtol, maxit, dinfo);
