@@ -960,7 +960,7 @@ namespace {
 
 // The history step of rk4_stage with opts.guess_steps = m: record the incoming p as the value of
 // the previous call's stage, then extrapolate stage k's record into p (k_guess, one launch).
-int stage_guess(pmgw_plan p, int k, double dt, double* pr) {
+int stage_guess(pmgw_plan p, int k, double dt, double* pr, hipStream_t st) {
   const int m = p->opts.guess_steps;
   const bool in_order = p->hist_k != 0 && k == p->hist_k % 5 + 1 && dt == p->hist_dt;
   if (!in_order)
@@ -988,7 +988,7 @@ int stage_guess(pmgw_plan p, int k, double dt, double* pr) {
   if (g.store < 0 && g.nsrc == 0) return PMGW_OK;
   const int64_t n2d = p->off2d[p->ntanks];
   const int64_t blocks = std::min<int64_t>((n2d + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_guess, dim3((unsigned)blocks), dim3(256), 0, p->stream, pr,
+  hipLaunchKernelGGL(k_guess, dim3((unsigned)blocks), dim3(256), 0, st, pr,
                      reinterpret_cast<double*>(p->ws + p->hist_off), n2d, g);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "initial-guess kernel launch");
@@ -1032,15 +1032,13 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   if (e == hipSuccess) e = hipStreamWaitEvent(p->setup_side, p->setup_fork, 0);
   if (e != hipSuccess) return hip_fail(e, "set-up fork");
   if ((rc = setup_kernels(p, p->setup_side))) return rc;
+  // the initial guess touches only p and its record: it runs on the set-up stream as well
+  if (p->opts.guess_steps > 0 && (rc = stage_guess(p, k, dt, pr, p->setup_side))) return rc;
   e = hipEventRecord(p->setup_join, p->setup_side);
   if (e != hipSuccess) return hip_fail(e, "set-up join");
   p->geometry_set = true;
   rc = launch_rk_all(p, 1, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
   if (rc) return rc;
-  if (p->opts.guess_steps > 0) {
-    rc = stage_guess(p, k, dt, pr);
-    if (rc) return rc;
-  }
   e = hipStreamWaitEvent(p->stream, p->setup_join, 0);
   if (e != hipSuccess) return hip_fail(e, "set-up join");
   pmgw_info_dev* dinfo = info_dev ? reinterpret_cast<pmgw_info_dev*>(info_dev)
