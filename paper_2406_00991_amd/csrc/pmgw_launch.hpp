@@ -38,7 +38,8 @@ template <int NZ>
 void launch_k_solve_res(unsigned grid, int threads, size_t lds, hipStream_t st,
                         const SolveArgs& a);
 
-// Arguments of the stage kernels k_rk_pre (which = 0), k_rk_force (1), k_rk_post (2).
+// Arguments of the stage kernels: k_rk_pre (which = 0), k_rk_force and k_rk_rhs (1),
+// k_rk_update (2).
 struct RkArgs {
   const TankDesc* descs;
   const int32_t* ids;

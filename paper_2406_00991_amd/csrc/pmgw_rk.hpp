@@ -12,9 +12,8 @@
 //   k_rk_rhs    right-hand side rho/(b dt) Div^new(u*, w*) inside, 0 on the surface row and
 //               -rho/(b dt)(h_x u* + w*) on the bed row (eq. poissonp, eq. bcpd, eq. bcpdneu).
 //   (solve)     flexible GMRES / p-multigrid for the dynamic pressure p.
-//   k_rk_post   (G_x, G_z) = Grad^old p; K_u <- a K_u + dt (F_u - G_x/rho), K_w likewise;
-//               r = (u + b K_u, w + b K_w).
-//   k_rk_filter per component: u <- filter(r_u), w <- filter(r_w) in x and sigma.
+//   k_rk_update per component: (G_x, G_z) = Grad^old p; K_u <- a K_u + dt (F_u - G_x/rho),
+//               K_w likewise; u <- filter(u + b K_u), w <- filter(w + b K_w) in x and sigma.
 //
 // Model options (RkCoef): lin = the linearised equations (eq. NSElin, eq. linFS): F without the
 // advection terms, eta_t = w~, and the host sets the geometry with eta = 0 (z1, zeroed by
@@ -136,7 +135,7 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_pre(const TankDesc* __rest
 
 // Forcing and provisional velocity of one component per workgroup: blockIdx.y = 0 for u (level
 // temporaries t1..t3 of the finest level), 1 for w (r1, r2, b as temporaries: r1 and r2 are
-// written by k_rk_post later, b by k_rk_rhs after both components).
+// written by k_rk_update later, b by k_rk_rhs after both components).
 template <int NZ>
 __global__ void __launch_bounds__(kStageThreads) k_rk_force(const TankDesc* __restrict__ descs,
                                                   const int32_t* __restrict__ ids, char* ws,
@@ -216,14 +215,19 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_rhs(const TankDesc* __rest
   }
 }
 
-// Projection and velocity update: K <- a K + dt (F - Grad^old p / rho), r = (u, w) + b K.
+// Projection, velocity update and filter, one velocity component per workgroup
+// (blockIdx.y = 0 for u, 1 for w): G = Grad^old p (G_x = D_x p + sigma_x D_s p, G_z = D_s p / d),
+// K <- a K + dt (F - G / rho), r = q + b K, then q <- filter(r) in x and sigma. Temporaries:
+// u uses t1, t2, t3 of the finest level and r1; w uses b and us (both free after the solve) and
+// r2.
 template <int NZ>
-__global__ void __launch_bounds__(kStageThreads) k_rk_post(const TankDesc* __restrict__ descs,
-                                                 const int32_t* __restrict__ ids, char* ws,
-                                                 RkCoef cf, const double* p, double* u, double* w,
-                                                 double* Ku, double* Kw, RkBufs rb, int fftb) {
+__global__ void __launch_bounds__(kStageThreads) k_rk_update(const TankDesc* __restrict__ descs,
+                                                   const int32_t* __restrict__ ids, char* ws,
+                                                   RkCoef cf, const double* p, double* u,
+                                                   double* w, double* Ku, double* Kw, RkBufs rb,
+                                                   int fftb) {
   const TankDesc& td = descs[ids[blockIdx.x]];
-  const int nx = td.nx, n = nx * NZ;
+  const int nx = td.nx, n = nx * NZ, comp = blockIdx.y;
   if (td.nz != NZ || nx < 8 || nx > 2048) return;
   Ctx<double> c;
   Lev<double> A;
@@ -231,53 +235,38 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_post(const TankDesc* __res
   const Geo<double> g = c.g;
   const gptr<const double> sig = A.sig;
   const gptr<const double> pp = as_global(p + td.off2d);
-  const gptr<const double> uu = as_global(u + td.off2d), wwp = as_global(w + td.off2d);
-  const gptr<double> ku = as_global(Ku + td.off2d), kw = as_global(Kw + td.off2d);
-  const gptr<const double> Fu = as_global(rb.Fu + td.off2d), Fw = as_global(rb.Fw + td.off2d);
-  const gptr<double> r1 = as_global(rb.r1 + td.off2d), r2 = as_global(rb.r2 + td.off2d);
-  const gptr<double> t1 = A.t1, t2 = A.t2;
-  col_dsig<double, NZ>(nx, A.Ds, pp, t1);
+  const gptr<double> q = as_global((comp == 0 ? u : w) + td.off2d);
+  const gptr<double> K = as_global((comp == 0 ? Ku : Kw) + td.off2d);
+  const gptr<const double> F = as_global((comp == 0 ? rb.Fu : rb.Fw) + td.off2d);
+  const gptr<double> r = as_global((comp == 0 ? rb.r1 : rb.r2) + td.off2d);
+  const gptr<double> ts = comp == 0 ? A.t1 : as_global(rb.b + td.off2d);
+  const gptr<double> tf = comp == 0 ? A.t3 : as_global(rb.us + td.off2d);
+  const gptr<double> t2 = A.t2;
+  const gptr<const double> fx = gcp<double>(ws, td.filtx);
+  const gptr<const double> fz = gcp<double>(ws, td.filtz);
+  col_dsig<double, NZ>(nx, A.Ds, pp, ts);
   __syncthreads();
-  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb, [=](int j, int i) { return pp[j * nx + i]; },
-                  [=](int j, int i, double v) { t2[j * nx + i] = v; });
+  if (comp == 0)
+    dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb, [=](int j, int i) { return pp[j * nx + i]; },
+                    [=](int j, int i, double v) { t2[j * nx + i] = v; });
   const double ir = 1.0 / cf.rho;
   for (int e = tid(); e < n; e += nthr()) {
     const int j = e / nx, i = e - j * nx;
-    const double gx = t2[e] + (g.ao[i] + g.bo[i] * sig[j]) * t1[e];
-    const double gz = t1[e] * g.ido[i];
-    const double a = cf.a * ku[e] + cf.dt * (Fu[e] - gx * ir);
-    const double bb = cf.a * kw[e] + cf.dt * (Fw[e] - gz * ir);
+    const double gr = comp == 0 ? t2[e] + (g.ao[i] + g.bo[i] * sig[j]) * ts[e]
+                                : ts[e] * g.ido[i];
+    const double a = cf.a * K[e] + cf.dt * (F[e] - gr * ir);
     const bool held = cf.noslip && j == NZ - 1;  // the update itself runs unheld, as filtered
-    ku[e] = held ? 0.0 : a;
-    kw[e] = held ? 0.0 : bb;
-    r1[e] = uu[e] + cf.b * a;
-    r2[e] = wwp[e] + cf.b * bb;
+    K[e] = held ? 0.0 : a;
+    r[e] = q[e] + cf.b * a;
   }
-}
-
-// Filter of one updated component per workgroup (blockIdx.y = 0: u from r1 with t3 of the
-// finest level as temporary; 1: w from r2 with b, free after the solve), in x then sigma.
-template <int NZ>
-__global__ void __launch_bounds__(kStageThreads) k_rk_filter(const TankDesc* __restrict__ descs,
-                                                   const int32_t* __restrict__ ids, char* ws,
-                                                   RkCoef cf, double* u, double* w, RkBufs rb,
-                                                   int fftb) {
-  const TankDesc& td = descs[ids[blockIdx.x]];
-  const int nx = td.nx, comp = blockIdx.y;
-  if (td.nz != NZ || nx < 8 || nx > 2048) return;
-  stage_twiddles(gcp<cpx<double>>(ws, td.tw[0]), gcp<cpx<float>>(ws, td.tw[1]), nx, fftb);
-  const gptr<const double> src = as_global((comp == 0 ? rb.r1 : rb.r2) + td.off2d);
-  const gptr<double> dst = as_global((comp == 0 ? u : w) + td.off2d);
-  const gptr<double> t3 = comp == 0 ? gmp<double>(ws, td.a3) : as_global(rb.b + td.off2d);
-  const gptr<const double> fx = gcp<double>(ws, td.filtx);
-  const gptr<const double> fz = gcp<double>(ws, td.filtz);
-  spectral_rows<double>(NZ, nx, td.log2nx, fftb, [=](int j, int i) { return src[j * nx + i]; },
+  __syncthreads();
+  spectral_rows<double>(NZ, nx, td.log2nx, fftb, [=](int j, int i) { return r[j * nx + i]; },
                         [=](int k, cpx<double> v) { return filt_mul(fx, nx, k, v); },
-                        [=](int j, int i, double v) { t3[j * nx + i] = v; });
-  col_dsig<double, NZ>(nx, fz, t3, dst);
+                        [=](int j, int i, double v) { tf[j * nx + i] = v; });
+  col_dsig<double, NZ>(nx, fz, tf, q);
   if (cf.noslip) {
     __syncthreads();
-    for (int i = tid(); i < nx; i += nthr()) dst[(NZ - 1) * nx + i] = 0.0;
+    for (int i = tid(); i < nx; i += nthr()) q[(NZ - 1) * nx + i] = 0.0;
   }
 }
 

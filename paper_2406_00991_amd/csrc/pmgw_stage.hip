@@ -22,10 +22,8 @@ void launch_k_rk(int which, unsigned grid, size_t lds, hipStream_t st, const RkA
     hipLaunchKernelGGL(k_rk_rhs<NZ>, dim3(grid), blk, lds, st, a.descs, a.ids, a.ws, a.cf, a.rb,
                        a.fftb);
   } else {
-    hipLaunchKernelGGL(k_rk_post<NZ>, dim3(grid), blk, lds, st, a.descs, a.ids, a.ws, a.cf, a.pr,
-                       a.uo, a.wo, a.Ku, a.Kw, a.rb, a.fftb);
-    hipLaunchKernelGGL(k_rk_filter<NZ>, dim3(grid, 2), blk, lds, st, a.descs, a.ids, a.ws, a.cf,
-                       a.uo, a.wo, a.rb, a.fftb);
+    hipLaunchKernelGGL(k_rk_update<NZ>, dim3(grid, 2), blk, lds, st, a.descs, a.ids, a.ws, a.cf,
+                       a.pr, a.uo, a.wo, a.Ku, a.Kw, a.rb, a.fftb);
   }
 }
 
