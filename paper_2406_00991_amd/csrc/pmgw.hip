@@ -729,6 +729,19 @@ int geometry_kernel(pmgw_plan p, const double* h, const double* eo, const double
   return PMGW_OK;
 }
 
+// The surface part of a stage and the metrics of its two geometries (k_rk_pre_geometry), on the
+// plan's stream.
+int pre_geometry_kernel(pmgw_plan p, const RkCoef& cf, const double* h, const double* u,
+                        const double* w, double* eta, double* Keta, const RkBufs& rb) {
+  const TankDesc* d = reinterpret_cast<const TankDesc*>(p->ws + p->desc_off);
+  hipLaunchKernelGGL(k_rk_pre_geometry, dim3(p->ntanks), dim3(256),
+                     lds_bytes(kGeoFftBytes, p->maxnx_all), p->stream, d, p->ws, cf, h, u, w, eta,
+                     Keta, rb);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "stage surface kernel launch");
+  return PMGW_OK;
+}
+
 // The smoother's set-up from the metrics: block inverses, and the bed-line and direct coarse
 // solve set-ups when enabled, on stream st.
 int setup_kernels(pmgw_plan p, hipStream_t st) {
@@ -1019,12 +1032,9 @@ extern "C" int rk4_stage(pmgw_plan p, int32_t k, double dt, const double* h, dou
   cf.lin = p->opts.linear;
   cf.noslip = p->opts.no_slip;
   const RkBufs rb = rk_bufs(p->ws + p->rk_off, p->off2d[p->ntanks], p->off1d[p->ntanks]);
-  rc = launch_rk_all(p, 0, cf, u, w, eta, Ku, Kw, Keta, pr, rb);
-  if (rc) return rc;
-  // the linearised model keeps the still-water geometry: k_rk_pre leaves rb.z1 at zero
-  rc = cf.lin ? geometry_kernel(p, h, rb.z1, rb.z1, p->stream)
-              : geometry_kernel(p, h, rb.eo, eta, p->stream);
-  if (rc) return rc;
+  // surface update and the metrics of the old and new surface (the linearised model keeps the
+  // still-water geometry)
+  if ((rc = pre_geometry_kernel(p, cf, h, u, w, eta, Keta, rb))) return rc;
   // the smoother set-up needs only the metrics: it runs on the set-up stream while the forcing
   // and right-hand-side kernels run here, and is joined before the solve
   if ((rc = ensure_setup_stream(p))) return rc;

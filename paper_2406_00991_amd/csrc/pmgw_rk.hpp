@@ -98,14 +98,13 @@ __device__ __forceinline__ cpx<double> filt_mul(gptr<const double> fx, int N, in
   return {v.re * f, v.im * f};
 }
 
-template <int NZ>
-__global__ void __launch_bounds__(kStageThreads) k_rk_pre(const TankDesc* __restrict__ descs,
-                                                const int32_t* __restrict__ ids, char* ws,
-                                                RkCoef cf, const double* u, const double* w,
-                                                double* eta, double* Keta, RkBufs rb, int fftb) {
-  const TankDesc& td = descs[ids[blockIdx.x]];
+// The surface part of a stage for one tank (every thread of the workgroup calls it; ends with a
+// barrier): eta_t = -u~ D_x eta + w~ (w~ alone in the linearised model), K_eta <- a K_eta +
+// dt eta_t, the old surface kept in eo, eta <- filter_x(eta + b K_eta); z1 <- 0.
+__device__ __forceinline__ void rk_pre_tank(const TankDesc& td, char* ws, const RkCoef& cf,
+                                            const double* u, const double* w, double* eta,
+                                            double* Keta, const RkBufs& rb, int fftb) {
   const int nx = td.nx;
-  if (td.nz != NZ || nx < 8 || nx > 2048) return;
   const gptr<const double> u0 = as_global(u + td.off2d);
   const gptr<const double> w0 = as_global(w + td.off2d);
   const gptr<double> e = as_global(eta + td.off1d);
@@ -131,6 +130,16 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_pre(const TankDesc* __rest
   spectral_rows<double>(1, nx, td.log2nx, fftb, [=](int, int i) { return e[i]; },
                         [=](int n, cpx<double> v) { return filt_mul(fx, nx, n, v); },
                         [=](int, int i, double v) { e[i] = v; });
+}
+
+template <int NZ>
+__global__ void __launch_bounds__(kStageThreads) k_rk_pre(const TankDesc* __restrict__ descs,
+                                                const int32_t* __restrict__ ids, char* ws,
+                                                RkCoef cf, const double* u, const double* w,
+                                                double* eta, double* Keta, RkBufs rb, int fftb) {
+  const TankDesc& td = descs[ids[blockIdx.x]];
+  if (td.nz != NZ || td.nx < 8 || td.nx > 2048) return;
+  rk_pre_tank(td, ws, cf, u, w, eta, Keta, rb, fftb);
 }
 
 // Forcing and provisional velocity of one component per workgroup: blockIdx.y = 0 for u (level

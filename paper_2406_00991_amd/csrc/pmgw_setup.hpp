@@ -3,6 +3,7 @@
 // block-inversion kernels.
 #pragma once
 #include "pmgw_kernels.hpp"
+#include "pmgw_rk.hpp"
 
 namespace pmgw {
 
@@ -120,13 +121,10 @@ constexpr int kGeoFftBytes = 32768;   // the geometry kernel: 2 x 32 KB of FFT L
 // cbar = <1/(d_o d_n)> and ebar = <(1 + h_x^2)/d_o> of the flat-mode operator, the mode-step
 // damping factor min(1, 2 / (1 + (r/2)^0.4)) with r = max c / min c, c = 1/(d_o d_n), and float32
 // copies for mixed plans.
-__global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ descs, char* ws,
-                                                  const double* h, const double* eo,
-                                                  const double* en) {
-  __shared__ double red[16];
-  const TankDesc td = descs[blockIdx.x];
+// The metrics of one tank (every thread of the workgroup calls it); red: 16 doubles of LDS.
+__device__ __forceinline__ void geometry_tank(const TankDesc& td, char* ws, const double* h,
+                                              const double* eo, const double* en, double* red) {
   const int nx = td.nx;
-  if (nx < 8 || nx > 2048) return;
   double* G = mp<double>(ws, td.geo64);
   const double* hh = h + td.off1d;
   const double* e0 = eo + td.off1d;
@@ -183,6 +181,32 @@ __global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ d
     const double r = cmax * icmax;
     S[3] = fmin(1.0, 2.0 / (1.0 + pow(0.5 * r, 0.4)));
   }
+}
+
+__global__ void __launch_bounds__(256) k_geometry(const TankDesc* __restrict__ descs, char* ws,
+                                                  const double* h, const double* eo,
+                                                  const double* en) {
+  __shared__ double red[16];
+  const TankDesc& td = descs[blockIdx.x];
+  if (td.nx < 8 || td.nx > 2048) return;
+  geometry_tank(td, ws, h, eo, en, red);
+}
+
+// The surface part of a stage and then the metrics of the old and new surface, one workgroup
+// per tank (rk4_stage's first launch; the same arithmetic as k_rk_pre followed by k_geometry).
+// The linearised model's metrics use the still-water surface z1 for both geometries.
+__global__ void __launch_bounds__(256) k_rk_pre_geometry(const TankDesc* __restrict__ descs,
+                                                         char* ws, RkCoef cf, const double* h,
+                                                         const double* u, const double* w,
+                                                         double* eta, double* Keta, RkBufs rb) {
+  __shared__ double red[16];
+  const TankDesc& td = descs[blockIdx.x];
+  if (td.nx < 8 || td.nx > 2048) return;
+  rk_pre_tank(td, ws, cf, u, w, eta, Keta, rb, kGeoFftBytes);
+  __syncthreads();
+  const double* eo = cf.lin ? rb.z1 : rb.eo;
+  const double* en = cf.lin ? rb.z1 : eta;
+  geometry_tank(td, ws, h, eo, en, red);
 }
 
 // ----------------------------------------------------------------------------- block kernel
