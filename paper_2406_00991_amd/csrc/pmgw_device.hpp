@@ -476,13 +476,192 @@ __device__ __forceinline__ bool fft_by_wave(int N, int fftb) {
   return N >= 64 && N <= 512 && N * (nthr() >> 6) <= 2 * fft_cap<T>(fftb);
 }
 
+// ----------------------------------------------------------------------------- 16 x 16 transform
+//
+// Rows of N = 256 by the four-step split N = 16 x 16, sixteen lanes per (packed) row: lane t of a
+// group holds x[t + 16 r] in v[r]. A 16-point DFT in registers over r, the twiddles W_256^(t s),
+// one transpose through LDS and a second 16-point DFT leave X[t + 16 u] in v[u]: one LDS round
+// trip per transform instead of one per radix-4 pass.
+
+// W_16^e a for the exponents e = n1 k1 (n1, k1 < 4) of the 4 x 4 split of a 16-point DFT.
+template <typename T>
+__device__ __forceinline__ cpx<T> fs16_twiddle(cpx<T> a, int e) {
+  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+  const T h = T(0.70710678118654752440);
+  switch (e) {
+    case 1: return {c1 * a.re + s1 * a.im, c1 * a.im - s1 * a.re};
+    case 2: return {h * (a.re + a.im), h * (a.im - a.re)};
+    case 3: return {s1 * a.re + c1 * a.im, s1 * a.im - c1 * a.re};
+    case 4: return {a.im, -a.re};
+    case 6: return {h * (a.im - a.re), -h * (a.re + a.im)};
+    case 9: return {-c1 * a.re - s1 * a.im, s1 * a.re - c1 * a.im};
+    default: return a;
+  }
+}
+
+// Forward 4-point DFT in place.
+template <typename T>
+__device__ __forceinline__ void fs16_dft4(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3) {
+  const cpx<T> s02 = cadd(a0, a2), d02 = csub(a0, a2), s13 = cadd(a1, a3), d13 = csub(a1, a3);
+  const cpx<T> md = {d13.im, -d13.re};   // -i (a1 - a3)
+  a0 = cadd(s02, s13);
+  a1 = cadd(d02, md);
+  a2 = csub(s02, s13);
+  a3 = csub(d02, md);
+}
+
+// Forward 16-point DFT of v in registers: with n = n1 + 4 n2 and k = k1 + 4 k2,
+// X[k1 + 4 k2] = sum_n1 W_4^(n1 k2) W_16^(n1 k1) sum_n2 v[n1 + 4 n2] W_4^(n2 k1).
+template <typename T>
+__device__ __forceinline__ void fs16_dft(cpx<T> (&v)[16]) {
+  cpx<T> a[4][4];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    cpx<T> q0 = v[n1], q1 = v[n1 + 4], q2 = v[n1 + 8], q3 = v[n1 + 12];
+    fs16_dft4(q0, q1, q2, q3);
+    a[n1][0] = q0;
+    a[n1][1] = fs16_twiddle(q1, n1);
+    a[n1][2] = fs16_twiddle(q2, 2 * n1);
+    a[n1][3] = fs16_twiddle(q3, 3 * n1);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cpx<T> q0 = a[0][k1], q1 = a[1][k1], q2 = a[2][k1], q3 = a[3][k1];
+    fs16_dft4(q0, q1, q2, q3);
+    v[k1] = q0;
+    v[k1 + 4] = q1;
+    v[k1 + 8] = q2;
+    v[k1 + 12] = q3;
+  }
+}
+
+// Unscaled inverse 16-point DFT by the identity IDFT(v) = swap(DFT(swap(v))), where swap exchanges
+// the real and imaginary parts.
+template <typename T>
+__device__ __forceinline__ void fs16_idft(cpx<T> (&v)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = cpx<T>{v[k].im, v[k].re};
+  fs16_dft(v);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = cpx<T>{v[k].im, v[k].re};
+}
+
+// The transpose between the two 16-point passes, through the group's 256-element LDS row S: lane t
+// receives in v[q] what lane q held in v[t]. XOR-swizzled columns keep the 16 lanes of a write or
+// read on distinct banks. Only groups with a row (ok) touch S; the wavefront syncs are uniform.
+template <typename T>
+__device__ __forceinline__ void fs16_transpose(cpx<T> (&v)[16], lptr<cpx<T>> S, int t, bool ok) {
+  if (ok) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) lst<T>(S, s * 16 + (t ^ s), v[s]);
+  }
+  wave_sync();
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = lld<T>(S, t * 16 + (q ^ t));
+  }
+  wave_sync();
+}
+
+// F^-1 (m_k F v) of one packed row held by a group in the 16 x 16 layout (v[r] = x[t + 16 r]),
+// with the multiplier applied as v[u] = sm(t + 16 u, v[u]) between the passes.
+template <typename T, class SM, class TW>
+__device__ __forceinline__ void fs16_spectral(cpx<T> (&v)[16], TW tw, lptr<cpx<T>> S, int t,
+                                              bool ok, SM sm) {
+  fs16_dft(v);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = cmul(v[q], tw(q));   // W_256^(t q)
+  fs16_transpose(v, S, t, ok);
+  fs16_dft(v);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) v[u] = sm(t + 16 * u, v[u]);
+  fs16_idft(v);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const cpx<T> w = tw(q);
+    v[q] = cmul(v[q], cpx<T>{w.re, -w.im});
+  }
+  fs16_transpose(v, S, t, ok);
+  fs16_idft(v);
+}
+
+// Lane roles of the 16 x 16 row transforms of a workgroup: group t = lane & 15 of LDS slot
+// (lane >> 4) nw + wavefront; the slots are bounded by the FFT buffer (2 fftb bytes).
+template <typename T>
+struct Fs16Lanes {
+  int t, slot, nslots;
+  lptr<cpx<T>> S;
+  lptr<const cpx<T>> tw;
+  __device__ __forceinline__ Fs16Lanes(int fftb) {
+    const int nw = nthr() >> 6;
+    t = tid() & 15;
+    slot = ((tid() & 63) >> 4) * nw + (tid() >> 6);
+    nslots = min(4 * nw, (2 * fft_cap<T>(fftb)) / 256);
+    S = as_lds(fft_buf<T>() + min(slot, nslots - 1) * 256);
+    tw = as_lds((const cpx<T>*)lds_tw<T>(fftb, 256));
+  }
+};
+
+// Largest level the operator runs the 16 x 16 transforms on. The 33-row operators keep the
+// radix-4 path: the calls of the transform in the 33-row solve kernel's body raised its register
+// spills enough to slow its 64 x 33 solves by a quarter.
+constexpr int kFs16MaxRows = 17;
+
+// Whether the 16 x 16 row transforms apply: float64 rows of N = 256 and room for one slot.
+template <typename T>
+__device__ __forceinline__ bool fs16_fits(int N, int fftb) {
+  return sizeof(T) == 8 && N == 256 && 2 * fft_cap<T>(fftb) >= N;
+}
+
+// spectral_rows by the 16 x 16 transform: each group reads its row pair from ld and writes it
+// through st directly from registers. Ends with a barrier. Not inlined: the unrolled transforms
+// at every call site would make the callers too long for short branches.
+template <typename T, class LD, class SM, class ST>
+__device__ __noinline__ void spectral_rows_fs(int nrows, int fftb, LD ld, SM sm, ST st) {
+  const int npairs = (nrows + 1) >> 1;
+  const Fs16Lanes<T> g(fftb);
+  cpx<T> w[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) w[q] = lld<T>(g.tw, (g.t * q) & 255);
+  for (int base = 0; base < npairs; base += g.nslots) {
+    const int pp = base + g.slot;
+    const bool ok = g.slot < g.nslots && pp < npairs;
+    const int ra = 2 * pp;
+    cpx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int n = g.t + 16 * r;
+      v[r] = {T(0), T(0)};
+      if (ok) v[r] = {ld(ra, n), (ra + 1 < nrows) ? ld(ra + 1, n) : T(0)};
+    }
+    fs16_spectral(v, [&](int q) { return w[q]; }, g.S, g.t, ok, sm);
+    if (ok) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        st(ra, g.t + 16 * r, v[r].re);
+        if (ra + 1 < nrows) st(ra + 1, g.t + 16 * r, v[r].im);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // A real spectral operator along x on `nrows` real rows: F^-1 (m_k F f) (paper Sec. 3.5 for D_x,
 // Sec. 3.6 for the filter). Two real rows are packed into one complex FFT; the multiplier must
-// satisfy m_{-k} = conj(m_k) (a real operator) so that real and imaginary parts stay separate. ld(j, i) reads input
-// row j at column i; sm(k, v) returns m_k v / N for the unscaled inverse FFT; st(j, i, v) writes
-// the result. fftb: bytes of one half of the FFT LDS buffer. Ends with a barrier.
-template <typename T, class LD, class SM, class ST>
+// satisfy m_{-k} = conj(m_k) (a real operator) so that real and imaginary parts stay separate.
+// ld(j, i) reads input row j at column i; sm(k, v) returns m_k v / N for the unscaled inverse FFT;
+// st(j, i, v) writes the result. fftb: bytes of one half of the FFT LDS buffer. Ends with a
+// barrier.
+// FS = false keeps float64 rows of N = 256 on the radix-4 path (no call to the 16 x 16 transform
+// in the caller).
+template <typename T, bool FS = true, class LD, class SM, class ST>
 __device__ void spectral_rows(int nrows, int N, int log2N, int fftb, LD ld, SM sm, ST st) {
+  if constexpr (FS && sizeof(T) == 8) {
+    if (fs16_fits<T>(N, fftb)) {
+      spectral_rows_fs<T>(nrows, fftb, ld, sm, st);
+      return;
+    }
+  }
   const int npairs = (nrows + 1) >> 1;
   const cpx<T>* tw = lds_tw<T>(fftb, N);
   if (fft_by_wave<T>(N, fftb)) {
@@ -546,10 +725,59 @@ struct DxMul {
 };
 
 // D_x of `nrows` real rows.
-template <typename T, class LD, class ST>
+template <typename T, bool FS = true, class LD, class ST>
 __device__ __forceinline__ void dx_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld,
                                         ST st) {
-  spectral_rows<T>(nrows, N, log2N, fftb, ld, DxMul<T>{N, kfac}, st);
+  spectral_rows<T, FS>(nrows, N, log2N, fftb, ld, DxMul<T>{N, kfac}, st);
+}
+
+// dx2_rows by the 16 x 16 transform (float64, N = 256): per row pair, p_x = D_x in from ld,
+// stored through stx; g = mid(j, i, p_x) formed in registers (mid's global reads issued before
+// the stores of p_x); D_x g stored through sto. Ends with a barrier. Not inlined (see
+// spectral_rows_fs).
+template <typename T, class SM, class LD, class STX, class MID, class STO>
+__device__ __noinline__ void dx2_rows_fs(int nrows, int fftb, SM sm, LD ld, STX stx, MID mid,
+                                         STO sto) {
+  const int npairs = (nrows + 1) >> 1;
+  const Fs16Lanes<T> g(fftb);
+  for (int base = 0; base < npairs; base += g.nslots) {
+    const int pp = base + g.slot;
+    const bool ok = g.slot < g.nslots && pp < npairs;
+    const int ra = 2 * pp;
+    const bool two = ra + 1 < nrows;
+    cpx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int n = g.t + 16 * r;
+      v[r] = {T(0), T(0)};
+      if (ok) v[r] = {ld(ra, n), two ? ld(ra + 1, n) : T(0)};
+    }
+    fs16_spectral(v, [&](int q) { return lld<T>(g.tw, (g.t * q) & 255); }, g.S, g.t, ok, sm);
+    if (ok) {
+      cpx<T> gv[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = g.t + 16 * r;
+        gv[r] = {mid(ra, n, v[r].re), two ? mid(ra + 1, n, v[r].im) : T(0)};
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = g.t + 16 * r;
+        stx(ra, n, v[r].re);
+        if (two) stx(ra + 1, n, v[r].im);
+        v[r] = gv[r];
+      }
+    }
+    fs16_spectral(v, [&](int q) { return lld<T>(g.tw, (g.t * q) & 255); }, g.S, g.t, ok, sm);
+    if (ok) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        sto(ra, g.t + 16 * r, v[r].re);
+        if (two) sto(ra + 1, g.t + 16 * r, v[r].im);
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // Between the two passes of dx2_rows: the wavefront's rows of p_x = D_x in (packed pairs in LDS)
@@ -606,14 +834,24 @@ __device__ __forceinline__ void wave_mid_pairs(cpx<T>* A, int nr, int N, int lan
 // before the call. Otherwise, and always for float64 rows (whose doubled register footprint in
 // the fused form made the float64 solve slower), the two passes run one after the other, the
 // second reading p_x back through ldx. Ends with a barrier.
-template <typename T, class LD, class STX, class LDX, class MID, class STO>
+//
+// FS (float64 rows of N = 256): both passes by the 16 x 16 transform in one call, each group
+// keeping its row pair in registers from the first pass to the second; as on the fused float32
+// path, mid may then read only fields completed before the call. FS = false: the radix-4 path.
+template <typename T, bool FS = true, class LD, class STX, class LDX, class MID, class STO>
 __device__ void dx2_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld, STX stx, LDX ldx,
                          MID mid, STO sto) {
   const DxMul<T> sm{N, kfac};
+  if constexpr (FS && sizeof(T) == 8) {
+    if (fs16_fits<T>(N, fftb)) {
+      dx2_rows_fs<T>(nrows, fftb, sm, ld, stx, mid, sto);
+      return;
+    }
+  }
   if (sizeof(T) == 8 || !fft_by_wave<T>(N, fftb)) {
-    spectral_rows<T>(nrows, N, log2N, fftb, ld, sm, stx);
-    spectral_rows<T>(nrows, N, log2N, fftb, [=](int j, int i) { return mid(j, i, ldx(j, i)); },
-                     sm, sto);
+    spectral_rows<T, false>(nrows, N, log2N, fftb, ld, sm, stx);
+    spectral_rows<T, false>(nrows, N, log2N, fftb,
+                            [=](int j, int i) { return mid(j, i, ldx(j, i)); }, sm, sto);
     return;
   }
   if constexpr (sizeof(T) == 4) {
@@ -1220,11 +1458,14 @@ __device__ void col_prolong_add(int nx, gptr<const T> P_, gptr<const T> xc, gptr
 // B and C run fused per wavefront (dx2_rows), so C reads P_x from LDS without a barrier; a
 // barrier after A makes t1 complete first. t1_ready: t1 already holds D_s in (A is skipped).
 // keep_t1: in FIN_COLSTEP, leave D_s of the updated x in t1.
-template <typename T, int NZ>
+// FS: float64 rows of N = 256 by the 16 x 16 transform (by default on levels of up to
+// kFs16MaxRows rows).
+template <typename T, int NZ, bool FS = (NZ <= kFs16MaxRows)>
 __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int mode,
                                          gptr<const T> in, gptr<T> out, gptr<const T> f,
                                          gptr<T> x, T omega, bool t1_ready = false,
                                          bool keep_t1 = false, gptr<T> fc = gptr<T>(nullptr)) {
+  constexpr bool kFs16 = FS;
   const int nx = c.nx;
   const gptr<T> t1 = L.t1;
   const gptr<T> t2 = L.t2;
@@ -1233,16 +1474,15 @@ __device__ __forceinline__ void op_apply(const Ctx<T>& c, const Lev<T>& L, int m
   const Geo<T> g = c.g;
   if (!t1_ready) {
     col_dsig<T, NZ>(nx, L.Ds, in, t1);
-    // the fused float32 passes read t1 without a barrier of their own; float64 runs B and C
-    // apart, and B's closing barrier orders t1 for C
-    if constexpr (sizeof(T) == 4) __syncthreads();
+    // the fused passes read t1 without a barrier of their own; the float64 radix-4 path runs B
+    // and C apart, and B's closing barrier orders t1 for C
+    if (sizeof(T) == 4 || (kFs16 && fs16_fits<T>(nx, c.fftb))) __syncthreads();
   }
-  dx2_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
-              [=](int j, int i) { return in[j * nx + i]; },
-              [=](int j, int i, T v) { t2[j * nx + i] = v; },
-              [=](int j, int i) { return t2[j * nx + i]; },
-              [=](int j, int i, T px) { return px + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i]; },
-              [=](int j, int i, T v) { t3[j * nx + i] = v; });
+  dx2_rows<T, kFs16>(
+      NZ, nx, c.log2nx, c.kfac, c.fftb, [=](int j, int i) { return in[j * nx + i]; },
+      [=](int j, int i, T v) { t2[j * nx + i] = v; }, [=](int j, int i) { return t2[j * nx + i]; },
+      [=](int j, int i, T px) { return px + (g.ao[i] + g.bo[i] * sig[j]) * t1[j * nx + i]; },
+      [=](int j, int i, T v) { t3[j * nx + i] = v; });
   col_finish<T, NZ>(mode, nx, L.Ds, sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega,
                     keep_t1 ? t1 : gptr<T>(nullptr), L.R, fc);
   __syncthreads();
@@ -1341,10 +1581,11 @@ __device__ __forceinline__ void op_apply_T(const Ctx<T>& c, const Lev<T>& L, int
   const Geo<T> g = c.g;
   colT_start<T, NZ>(nx, L.Ds, L.sig, g, in, t1, t2);
   // no barrier: the next phase reads only `in`; t1 and t2 are read after its closing barrier
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
-             [=](int j, int i) { return (j == 0 || j == NZ - 1) ? T(0) : in[j * nx + i]; },
-             [=](int j, int i, T v) { t3[j * nx + i] = v; });
-  dx_rows<T>(NZ, nx, c.log2nx, c.kfac, c.fftb,
+  constexpr bool kFs16 = NZ <= kFs16MaxRows;
+  dx_rows<T, kFs16>(NZ, nx, c.log2nx, c.kfac, c.fftb,
+                    [=](int j, int i) { return (j == 0 || j == NZ - 1) ? T(0) : in[j * nx + i]; },
+                    [=](int j, int i, T v) { t3[j * nx + i] = v; });
+  dx_rows<T, kFs16>(NZ, nx, c.log2nx, c.kfac, c.fftb,
              [=](int j, int i) { return t1[j * nx + i] - t3[j * nx + i]; },
              [=](int j, int i, T v) { out[j * nx + i] = v; });
   colT_finish<T, NZ>(mode, nx, L.Ds, L.sig, g, in, t1, t2, t3, out, f, x, L.colinv, omega);
