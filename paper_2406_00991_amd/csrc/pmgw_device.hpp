@@ -563,26 +563,41 @@ __device__ __forceinline__ void fs16_transpose(cpx<T> (&v)[16], lptr<cpx<T>> S, 
   wave_sync();
 }
 
-// F^-1 (m_k F v) of one packed row held by a group in the 16 x 16 layout (v[r] = x[t + 16 r]),
-// with the multiplier applied as v[u] = sm(t + 16 u, v[u]) between the passes.
-template <typename T, class SM, class TW>
-__device__ __forceinline__ void fs16_spectral(cpx<T> (&v)[16], TW tw, lptr<cpx<T>> S, int t,
-                                              bool ok, SM sm) {
+// Forward transform of one packed row held by a group in the 16 x 16 layout: in v[r] =
+// x[t + 16 r], out v[u] = X[t + 16 u].
+template <typename T>
+__device__ __forceinline__ void fs16_forward(cpx<T> (&v)[16], lptr<const cpx<T>> tw,
+                                             lptr<cpx<T>> S, int t, bool ok) {
   fs16_dft(v);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) v[q] = cmul(v[q], tw(q));   // W_256^(t q)
+  for (int q = 0; q < 16; ++q) v[q] = cmul(v[q], lld<T>(tw, (t * q) & 255));   // W_256^(t q)
   fs16_transpose(v, S, t, ok);
   fs16_dft(v);
-#pragma unroll
-  for (int u = 0; u < 16; ++u) v[u] = sm(t + 16 * u, v[u]);
+}
+
+// Unscaled inverse: in v[u] = X[t + 16 u], out v[r] = N x[t + 16 r].
+template <typename T>
+__device__ __forceinline__ void fs16_inverse(cpx<T> (&v)[16], lptr<const cpx<T>> tw,
+                                             lptr<cpx<T>> S, int t, bool ok) {
   fs16_idft(v);
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const cpx<T> w = tw(q);
+    const cpx<T> w = lld<T>(tw, (t * q) & 255);
     v[q] = cmul(v[q], cpx<T>{w.re, -w.im});
   }
   fs16_transpose(v, S, t, ok);
   fs16_idft(v);
+}
+
+// F^-1 (m_k F v) of one packed row in the 16 x 16 layout, with the multiplier applied as
+// v[u] = sm(t + 16 u, v[u]) between the passes.
+template <typename T, class SM>
+__device__ __forceinline__ void fs16_spectral(cpx<T> (&v)[16], lptr<const cpx<T>> tw,
+                                              lptr<cpx<T>> S, int t, bool ok, SM sm) {
+  fs16_forward(v, tw, S, t, ok);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) v[u] = sm(t + 16 * u, v[u]);
+  fs16_inverse(v, tw, S, t, ok);
 }
 
 // Lane roles of the 16 x 16 row transforms of a workgroup: group t = lane & 15 of LDS slot
@@ -620,9 +635,6 @@ template <typename T, class LD, class SM, class ST>
 __device__ __noinline__ void spectral_rows_fs(int nrows, int fftb, LD ld, SM sm, ST st) {
   const int npairs = (nrows + 1) >> 1;
   const Fs16Lanes<T> g(fftb);
-  cpx<T> w[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) w[q] = lld<T>(g.tw, (g.t * q) & 255);
   for (int base = 0; base < npairs; base += g.nslots) {
     const int pp = base + g.slot;
     const bool ok = g.slot < g.nslots && pp < npairs;
@@ -634,7 +646,7 @@ __device__ __noinline__ void spectral_rows_fs(int nrows, int fftb, LD ld, SM sm,
       v[r] = {T(0), T(0)};
       if (ok) v[r] = {ld(ra, n), (ra + 1 < nrows) ? ld(ra + 1, n) : T(0)};
     }
-    fs16_spectral(v, [&](int q) { return w[q]; }, g.S, g.t, ok, sm);
+    fs16_spectral(v, g.tw, g.S, g.t, ok, sm);
     if (ok) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -752,7 +764,7 @@ __device__ __noinline__ void dx2_rows_fs(int nrows, int fftb, SM sm, LD ld, STX 
       v[r] = {T(0), T(0)};
       if (ok) v[r] = {ld(ra, n), two ? ld(ra + 1, n) : T(0)};
     }
-    fs16_spectral(v, [&](int q) { return lld<T>(g.tw, (g.t * q) & 255); }, g.S, g.t, ok, sm);
+    fs16_spectral(v, g.tw, g.S, g.t, ok, sm);
     if (ok) {
       cpx<T> gv[16];
 #pragma unroll
@@ -768,7 +780,7 @@ __device__ __noinline__ void dx2_rows_fs(int nrows, int fftb, SM sm, LD ld, STX 
         v[r] = gv[r];
       }
     }
-    fs16_spectral(v, [&](int q) { return lld<T>(g.tw, (g.t * q) & 255); }, g.S, g.t, ok, sm);
+    fs16_spectral(v, g.tw, g.S, g.t, ok, sm);
     if (ok) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -880,10 +892,89 @@ __device__ void dx2_rows(int nrows, int N, int log2N, T kfac, int fftb, LD ld, S
   }
 }
 
-// Forward FFT of real rows, packed in pairs, into spec[(nrows+1)/2][N] (global). Barrier at end.
+// rows_fft_to_global by the 16 x 16 transform (float64, N = 256; not inlined, see
+// spectral_rows_fs).
 template <typename T, class LD>
+__device__ __noinline__ void rows_fft_to_global_fs(int nrows, int fftb, LD ld,
+                                                   gptr<cpx<T>> spec) {
+  const int npairs = (nrows + 1) >> 1;
+  const Fs16Lanes<T> g(fftb);
+  for (int base = 0; base < npairs; base += g.nslots) {
+    const int pp = base + g.slot;
+    const bool ok = g.slot < g.nslots && pp < npairs;
+    const int ra = 2 * pp;
+    cpx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int n = g.t + 16 * r;
+      v[r] = {T(0), T(0)};
+      if (ok) v[r] = {ld(ra, n), (ra + 1 < nrows) ? ld(ra + 1, n) : T(0)};
+    }
+    fs16_forward(v, g.tw, g.S, g.t, ok);
+    if (ok) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) gst<T>(spec, pp * 256 + g.t + 16 * u, v[u]);
+    }
+  }
+  __syncthreads();
+}
+
+// rows_ifft_from_global by the 16 x 16 transform (float64, N = 256). For an Axpy target with add,
+// every old value of x is loaded before the first store.
+template <typename T, class ST>
+__device__ __noinline__ void rows_ifft_from_global_fs(int nrows, int fftb,
+                                                      gptr<const cpx<T>> spec, ST st) {
+  const int npairs = (nrows + 1) >> 1;
+  const Fs16Lanes<T> g(fftb);
+  for (int base = 0; base < npairs; base += g.nslots) {
+    const int pp = base + g.slot;
+    const bool ok = g.slot < g.nslots && pp < npairs;
+    const int ra = 2 * pp;
+    const bool two = ra + 1 < nrows;
+    cpx<T> v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      v[u] = {T(0), T(0)};
+      if (ok) v[u] = gld<T>(spec, pp * 256 + g.t + 16 * u);
+    }
+    fs16_inverse(v, g.tw, g.S, g.t, ok);
+    if (!ok) continue;
+    if constexpr (std::is_same<ST, Axpy<T>>::value) {
+      cpx<T> o[16];
+      if (st.add) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int n = g.t + 16 * r;
+          o[r] = {st.x[ra * st.nx + n], two ? st.x[(ra + 1) * st.nx + n] : T(0)};
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int n = g.t + 16 * r;
+        st.x[ra * st.nx + n] = st.add ? o[r].re + st.w * v[r].re : st.w * v[r].re;
+        if (two) st.x[(ra + 1) * st.nx + n] = st.add ? o[r].im + st.w * v[r].im : st.w * v[r].im;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        st(ra, g.t + 16 * r, v[r].re);
+        if (two) st(ra + 1, g.t + 16 * r, v[r].im);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Forward FFT of real rows, packed in pairs, into spec[(nrows+1)/2][N] (global). Barrier at end.
+template <typename T, bool FS = true, class LD>
 __device__ void rows_fft_to_global(int nrows, int N, int log2N, int fftb, LD ld,
                                    gptr<cpx<T>> spec) {
+  if constexpr (FS && sizeof(T) == 8) {
+    if (fs16_fits<T>(N, fftb)) {
+      rows_fft_to_global_fs<T>(nrows, fftb, ld, spec);
+      return;
+    }
+  }
   const cpx<T>* tw = lds_tw<T>(fftb, N);
   const int npairs = (nrows + 1) >> 1;
   if (fft_by_wave<T>(N, fftb)) {
@@ -923,9 +1014,15 @@ __device__ void rows_fft_to_global(int nrows, int N, int log2N, int fftb, LD ld,
 
 // Inverse FFT (unscaled) of packed spectra spec[(nrows+1)/2][N]; st(j, i, v) receives the real
 // rows. Barrier at end.
-template <typename T, class ST>
+template <typename T, bool FS = true, class ST>
 __device__ void rows_ifft_from_global(int nrows, int N, int log2N, int fftb,
                                       gptr<const cpx<T>> spec, ST st) {
+  if constexpr (FS && sizeof(T) == 8) {
+    if (fs16_fits<T>(N, fftb)) {
+      rows_ifft_from_global_fs<T>(nrows, fftb, spec, st);
+      return;
+    }
+  }
   const cpx<T>* tw = lds_tw<T>(fftb, N);
   const int npairs = (nrows + 1) >> 1;
   if (fft_by_wave<T>(N, fftb)) {
@@ -1785,11 +1882,12 @@ __device__ __noinline__ void vcycle(Ctx<T> c_, LP lev_, int l_, KOpts o_) {
       }
     } else if (kind == MODE) {
       const gptr<const T> r = xzero ? gptr<const T>(L.f) : gptr<const T>(L.r);
-      rows_fft_to_global<T>(NZ, nx, c.log2nx, c.fftb,
+      rows_fft_to_global<T, (NZ <= kFs16MaxRows)>(NZ, nx, c.log2nx, c.fftb,
                             [=](int j, int i) { return r[j * nx + i]; }, L.spec);
       mode_matvec<T, NZ, TR>(nx, L.modeinv, L.spec);
       __syncthreads();
-      rows_ifft_from_global<T>(NZ, nx, c.log2nx, c.fftb, L.spec, Axpy<T>{L.x, nx, wm, !xzero});
+      rows_ifft_from_global<T, (NZ <= kFs16MaxRows)>(NZ, nx, c.log2nx, c.fftb, L.spec,
+                                                     Axpy<T>{L.x, nx, wm, !xzero});
       xzero = false;
       // the forward pair ends with the bed-line step
       if (!TR && o.bed_line && L.binv) bed_step<T, NZ>(c, L);
