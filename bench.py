@@ -142,13 +142,13 @@ class Tank:
         return self.pmgw.read_info(self.info[2 * first: 2 * (first + count)])
 
 
-def run_precision(wave, precision, steps, warmup, rtol, guess=0):
+def run_precision(wave, precision, steps, warmup, rtol, guess=0, correct=0):
     """RK4 stepping of one tank; guess = opts.guess_steps (0: each solve starts from the previous
-    stage's pressure)."""
+    stage's pressure), correct = opts.guess_correct."""
     import torch
 
     from paper_2406_00991_amd import pmgw
-    opts = pmgw.default_opts(guess_steps=guess) if guess else None
+    opts = pmgw.default_opts(guess_steps=guess, guess_correct=correct) if guess else None
     T = Tank(wave, precision, 5 * (steps + warmup), opts)
     dt = wave["dt"]
     for _ in range(warmup):
@@ -335,7 +335,7 @@ def run_stokes_layer(precision, warmup=2, rtol=1e-10):
             "closed_form_err": float(np.abs(u[near] - ue[near]).max() / t["U0m"])}
 
 
-def run_bar_flume(steps=12, warmup=2, rtol=1e-10, guess=4):
+def run_bar_flume(steps=12, warmup=2, rtol=1e-10, guess=4, correct=0):
     """The submerged-bar flume (1024 x 33, float64: on this bed the float32 cycle is near its
     stability edge; zones of one wavelength, stream-function wave
     H = 0.02 m, T = 2.02 s ramped in from still water, as the experiment starts): `steps` RK4
@@ -347,7 +347,8 @@ def run_bar_flume(steps=12, warmup=2, rtol=1e-10, guess=4):
     from paper_2406_00991_amd import pmgw
     from paper_2406_00991_amd import workloads as wl
     fl = wl.bar_flume()
-    T = Tank(fl, "fp64", 5 * (steps + warmup), pmgw.default_opts(guess_steps=guess))
+    T = Tank(fl, "fp64", 5 * (steps + warmup),
+             pmgw.default_opts(guess_steps=guess, guess_correct=correct))
     dev = lambda a: torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64,
                                  device="cuda")
     r, S, coef = dev(fl["r"]), dev(fl["S"]), dev(fl["coef"])
@@ -373,7 +374,8 @@ def run_bar_flume(steps=12, warmup=2, rtol=1e-10, guess=4):
                         "(37.4 m), depth 0.4 m to 0.1 m over the bar, generation and absorption "
                         "zones of one wavelength, stream-function wave H=0.02 m, T=2.02 s "
                         "ramped in over two periods from still water, float64, rtol 1e-10, steps "
-                        f"{warmup + 1}..{warmup + steps} from rest, relaxation after each step",
+                        f"{warmup + 1}..{warmup + steps} from rest, relaxation after each step; "
+                        f"initial guess opts.guess_steps {guess}, guess_correct {correct}",
             "value": 5 * steps / wall, "unit": "solves/s", "ms_per_step": 1e3 * wall / steps,
             "mean_iters": float(np.mean([i["iters"] for i in infos])),
             "max_iters": int(max(i["iters"] for i in infos)),
@@ -475,6 +477,9 @@ def main():
                     help="opts.guess_steps of the stepping plans: each stage's solve starts from "
                          "that stage's pressure extrapolated over this many previous steps "
                          "(0: from the previous stage's pressure)")
+    ap.add_argument("--guess-correct", type=int, default=1,
+                    help="opts.guess_correct of the stepping plans (with --guess-steps): add the "
+                         "previous stage's extrapolation error to the extrapolation")
     ap.add_argument("--no-prev", action="store_true",
                     help="skip the stepping with each solve started from the previous stage's "
                          "pressure (reported beside the headline)")
@@ -508,11 +513,12 @@ def main():
     wave = wl.stokes_wave(256, 17)
     rtol = 1e-10
     gs = args.guess_steps
-    res = {"mixed": run_precision(wave, "mixed", args.steps, args.warmup, rtol, gs)}
+    gc = args.guess_correct if gs else 0
+    res = {"mixed": run_precision(wave, "mixed", args.steps, args.warmup, rtol, gs, gc)}
     print(f"# mixed: {args.steps} steps in {res['mixed']['wall']:.3f} s", file=sys.stderr,
           flush=True)
     if not args.no_fp64:
-        res["fp64"] = run_precision(wave, "fp64", args.steps, args.warmup, rtol, gs)
+        res["fp64"] = run_precision(wave, "fp64", args.steps, args.warmup, rtol, gs, gc)
         print(f"# fp64: {args.steps} steps in {res['fp64']['wall']:.3f} s", file=sys.stderr,
               flush=True)
     if gs and not args.no_prev:
@@ -547,7 +553,9 @@ def main():
                                "pressure solves per step, each to rel. residual 1e-10",
                    "precision": "mixed", "rtol": rtol, "dt": wave["dt"],
                    "initial_guess": (f"each stage's pressure extrapolated over its previous {gs} "
-                                     "steps (opts.guess_steps)" if gs else
+                                     "steps (opts.guess_steps)"
+                                     + (", plus the previous stage's extrapolation error "
+                                        "(opts.guess_correct)" if gc else "") if gs else
                                      "the previous stage's pressure")},
         "solve": {"launches": mix["launches"], "mean_launch_ms": mix["solve_ms"],
                   "max_launch_ms": mix["max_ms"], "mean_iters": mix["iters"],
@@ -603,7 +611,7 @@ def main():
               f"mixed {out['stokes_layer']['mixed']['value']:.0f} solves/s", file=sys.stderr,
               flush=True)
     if not args.no_flume:
-        out["bar_flume"] = run_bar_flume()
+        out["bar_flume"] = run_bar_flume(correct=gc)
         print(f"# bar flume: {out['bar_flume']['value']:.1f} solves/s", file=sys.stderr,
               flush=True)
     if not args.no_cpu:

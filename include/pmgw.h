@@ -94,6 +94,8 @@ typedef struct {
                                (the previous stage's pressure); m in 2..5 = from the
                                extrapolation of the same stage's pressure over the previous m
                                steps, see rk4_stage [0]                                     */
+    int32_t guess_correct;  /* with guess_steps: 1 = add the previous stage's extrapolation
+                               error to the extrapolation, see rk4_stage [0]                 */
 } pmgw_opts;
 
 /* Per-tank outcome of a solve. status is one of the codes above for that tank. */
@@ -224,6 +226,11 @@ int poisson_solve(pmgw_plan plan, const double* b, double* p, double rtol, int32
  * reaches rtol; only its starting point differs. Workspace: 5 m n2d doubles more. The record's
  * slots are chosen on the host at each call, so a stage captured into a HIP graph replays the
  * slots of its capture: capture stages only of plans without guess_steps.
+ * With opts.guess_correct = 1 as well, a call whose previous call (in order) started from an
+ * extrapolation E' and returned p' starts from E + (p' - E') instead of E: the extrapolation
+ * error of one stage is close to that of the next, whose pressure moves along with it. Without
+ * such a previous call (first calls, after a restart of the record) it starts from E. The
+ * extrapolations are kept in n2d doubles more of workspace.
  */
 int rk4_stage(pmgw_plan plan, int32_t k, double dt, const double* h, double* u, double* w,
               double* eta, double* Ku, double* Kw, double* Keta, double* p, double rtol,

@@ -109,6 +109,10 @@ struct pmgw_plan_s {
   int hist_cnt[5] = {0, 0, 0, 0, 0}, hist_head[5] = {0, 0, 0, 0, 0};
   int hist_k = 0;
   double hist_dt = 0.0;
+  // opts.guess_correct: the last call's extrapolation (n2d doubles at eprev_off), valid when
+  // hist_eprev is set
+  int64_t eprev_off = 0;
+  bool hist_eprev = false;
   // tanks grouped by finest-level row count (3, 5, 9, 17, 33): one solve launch per class
   int64_t ids_off[5] = {0, 0, 0, 0, 0};
   std::vector<int32_t> ids[5];
@@ -434,6 +438,10 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   if (o.no_slip != 0 && o.no_slip != 1) return fail(PMGW_EINVAL, "no_slip must be 0 or 1");
   if (o.guess_steps != 0 && (o.guess_steps < 2 || o.guess_steps > 5))
     return fail(PMGW_EINVAL, "guess_steps must be 0 or in 2..5");
+  if (o.guess_correct != 0 && o.guess_correct != 1)
+    return fail(PMGW_EINVAL, "guess_correct must be 0 or 1");
+  if (o.guess_correct && !o.guess_steps)
+    return fail(PMGW_EINVAL, "guess_correct needs guess_steps");
   if (o.resident != 0 && o.resident != 1) return fail(PMGW_EINVAL, "resident must be 0 or 1");
   for (int t = 0; t < ntanks; ++t) {
     const int n = nx[t], M = nz[t] - 1;
@@ -600,6 +608,10 @@ int pmgw_plan_create(pmgw_plan* out, int32_t ntanks, const int32_t* nx, const in
   if (o.guess_steps > 0) {
     p->hist_off = cur;
     cur = align256(cur + 8LL * 5 * o.guess_steps * p->off2d[ntanks]);
+  }
+  if (o.guess_correct) {
+    p->eprev_off = cur;
+    cur = align256(cur + 8LL * p->off2d[ntanks]);
   }
   p->total = cur;
 
@@ -972,12 +984,15 @@ int launch_rk_all(pmgw_plan p, int which, const RkCoef& cf, double* u, double* w
 namespace {
 
 // The history step of rk4_stage with opts.guess_steps = m: record the incoming p as the value of
-// the previous call's stage, then extrapolate stage k's record into p (k_guess, one launch).
+// the previous call's stage, then extrapolate stage k's record into p, with opts.guess_correct
+// plus the previous call's extrapolation error (k_guess, one launch).
 int stage_guess(pmgw_plan p, int k, double dt, double* pr, hipStream_t st) {
   const int m = p->opts.guess_steps;
   const bool in_order = p->hist_k != 0 && k == p->hist_k % 5 + 1 && dt == p->hist_dt;
-  if (!in_order)
+  if (!in_order) {
     for (int s = 0; s < 5; ++s) p->hist_cnt[s] = p->hist_head[s] = 0;
+    p->hist_eprev = false;
+  }
   GuessArgs g{};
   g.store = -1;
   if (in_order) {
@@ -996,6 +1011,12 @@ int stage_guess(pmgw_plan p, int k, double dt, double* pr, hipStream_t st) {
       g.c[i - 1] = (i % 2 == 1 ? 1.0 : -1.0) * binom;
     }
   }
+  if (p->opts.guess_correct && g.nsrc > 0) {
+    g.eprev = reinterpret_cast<double*>(p->ws + p->eprev_off);
+    g.corr = p->hist_eprev ? 1 : 0;
+    g.save = 1;
+  }
+  p->hist_eprev = p->opts.guess_correct && g.nsrc > 0;
   p->hist_k = k;
   p->hist_dt = dt;
   if (g.store < 0 && g.nsrc == 0) return PMGW_OK;
@@ -1096,6 +1117,7 @@ extern "C" int pmgw_history_reset(pmgw_plan p) {
   if (!p) return fail(PMGW_EINVAL, "plan is NULL");
   for (int s = 0; s < 5; ++s) p->hist_cnt[s] = p->hist_head[s] = 0;
   p->hist_k = 0;
+  p->hist_eprev = false;
   return PMGW_OK;
 }
 

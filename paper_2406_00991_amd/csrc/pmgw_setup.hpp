@@ -23,8 +23,13 @@ struct GuessArgs {
   int nsrc;       // number of source slots (0: p is left as is)
   int src[5];
   double c[5];
+  double* eprev;  // the previous call's extrapolation (n2d doubles), or null
+  int corr;       // add the previous call's extrapolation error p - eprev
+  int save;       // keep this call's extrapolation in eprev
 };
 
+// p holds the previous call's result on entry: it is recorded (store), and replaced by the
+// extrapolation E = sum_i c_i hist[src_i] (nsrc > 0), plus p - eprev with corr.
 __global__ void __launch_bounds__(256) k_guess(double* p, double* hist, int64_t n2d,
                                                GuessArgs g) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n2d;
@@ -34,7 +39,9 @@ __global__ void __launch_bounds__(256) k_guess(double* p, double* hist, int64_t 
     if (g.nsrc > 0) {
       double s = 0.0;
       for (int i = 0; i < g.nsrc; ++i) s += g.c[i] * hist[g.src[i] * n2d + e];
-      p[e] = s;
+      const double corr = g.corr ? v - g.eprev[e] : 0.0;
+      if (g.save) g.eprev[e] = s;
+      p[e] = s + corr;
     }
   }
 }

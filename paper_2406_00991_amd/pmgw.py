@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
                 ("resident", ctypes.c_int32), ("class_threads", ctypes.c_int32 * 5),
                 ("class_resident", ctypes.c_int32 * 5), ("bed_line", ctypes.c_int32),
                 ("linear", ctypes.c_int32), ("no_slip", ctypes.c_int32),
-                ("guess_steps", ctypes.c_int32)]
+                ("guess_steps", ctypes.c_int32), ("guess_correct", ctypes.c_int32)]
 
 # finest-level row counts of the per-class options (class_threads, class_resident)
 CLASS_ROWS = (3, 5, 9, 17, 33)

@@ -52,7 +52,8 @@ def test_plan_rejects_bad_options_and_precision():
                 dict(nu1=-1), dict(threads=100), dict(threads=1024), dict(coarse_exact=2),
                 dict(class_threads={33: 96}), dict(class_threads=[0, 0, 0, 0, 1024]),
                 dict(class_resident={17: 3}), dict(class_resident={9: -1}), dict(bed_line=2),
-                dict(linear=2), dict(no_slip=-1), dict(guess_steps=1), dict(guess_steps=6)):
+                dict(linear=2), dict(no_slip=-1), dict(guess_steps=1), dict(guess_steps=6),
+                dict(guess_correct=1), dict(guess_steps=3, guess_correct=2)):
         rc, _ = _create([32], [9], [1.0], opts=pmgw.default_opts(**bad))
         assert rc == pmgw.EINVAL, bad
 
@@ -204,3 +205,18 @@ def test_plan3_layout_and_unbound_calls():
     assert L.pmgw3_laplacian_apply(h, None, None) == pmgw.EWORKSPACE
     assert L.pmgw3_set_geometry(h, None, None, None) == pmgw.EWORKSPACE
     L.pmgw3_plan_destroy(h)
+
+
+def test_guess_workspace():
+    """guess_steps = m adds 5 m n2d doubles of workspace (the stage records), guess_correct n2d
+    more (the last extrapolation)."""
+    n2d = 64 * 17
+    sizes = {}
+    for key, kw in (("none", {}), ("m4", dict(guess_steps=4)),
+                    ("m4c", dict(guess_steps=4, guess_correct=1))):
+        rc, h = _create([64], [17], [1.0], opts=pmgw.default_opts(**kw))
+        assert rc == 0
+        sizes[key] = pmgw.lib().pmgw_workspace_bytes(h)
+        pmgw.lib().pmgw_plan_destroy(h)
+    assert sizes["m4"] - sizes["none"] >= 8 * 5 * 4 * n2d
+    assert sizes["m4c"] - sizes["m4"] >= 8 * n2d
