@@ -165,6 +165,7 @@ def run_precision(wave, precision, steps, warmup, rtol, guess=0, correct=0):
     infos = T.infos(5 * warmup, 5 * steps)
     return dict(wall=wall, launches=launches, solve_ms=tot_ms / max(launches, 1), max_ms=max_ms,
                 iters=float(np.mean([i["iters"] for i in infos])),
+                iters_each=[int(i["iters"]) for i in infos],
                 max_iters=int(max(i["iters"] for i in infos)),
                 relres=float(max(i["relres"] for i in infos)),
                 status=sorted({i["status"] for i in infos}),
@@ -529,7 +530,8 @@ def main():
     nx, nz = wave["nx"], wave["nz"]
     solves = 5 * args.steps
     t_launch = mix["solve_ms"] * 1e-3
-    byts = solve_bytes(nx, nz, mix["iters"], 4)
+    # the mean of every timed solve's algorithmic bytes at its own iteration count
+    byts = float(np.mean([solve_bytes(nx, nz, k, 4) for k in mix["iters_each"]]))
     flops = solve_flops(nx, nz, mix["iters"])
     achieved = byts / t_launch / 1e9
     # the mixed plan's 256 x 17 tank runs the solve kernel with the LDS-resident V-cycle
