@@ -33,12 +33,6 @@ struct RkBufs {
   double *Fu, *Fw, *us, *ws, *b, *r1, *r2;
 };
 
-// The NZ-row transforms of the 512-thread stage kernels stay on the radix-4 path: a 512-thread
-// workgroup leaves 128 registers per lane, too few for the 16 x 16 transform's row of sixteen
-// complex values without spilling (measured: k_rk_force 49 us on the radix-4 path, 60 us on the
-// 16 x 16 one, at 256 x 17).
-constexpr bool kStageFs16 = false;
-
 inline int64_t rk_align(int64_t v) { return (v + 255) & ~int64_t(255); }
 
 inline int64_t rk_workspace_bytes(int64_t n2d, int64_t n1d) {
@@ -67,9 +61,12 @@ inline RkBufs rk_bufs(char* base, int64_t n2d, int64_t n1d) {
   return r;
 }
 
-// Threads per stage workgroup (one workgroup per tank): eight wavefronts, so that the row
-// transforms of a 17-row tank (nine packed pairs) run about one pair per wavefront.
-constexpr int kStageThreads = 512;
+// Threads per stage workgroup (one workgroup per tank, or per tank and velocity component): four
+// wavefronts, whose 16-lane groups take the row pairs of 256-point rows through the 16 x 16
+// transform in one round. Eight wavefronts would leave 128 registers per lane, too few for that
+// transform's sixteen complex values without spilling; on the radix-4 path they measured slower
+// at 256 x 17 (k_rk_force 49 against 44 us, k_rk_rhs 25 against 22, k_rk_update 41 against 35).
+constexpr int kStageThreads = 256;
 
 struct RkCoef {
   double a, b, dt, rho, g, nu;
@@ -183,8 +180,8 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_force(const TankDesc* __re
   const gptr<const double> ex = as_global(rb.etax + td.off1d);
   const gptr<double> t1 = A.t1, t2 = A.t2;
   // F <- Div^old Grad^old f; leaves t1 = D_s f, t2 = D_x f
-  op_apply<double, NZ, kStageFs16>(cold, A, FIN_FULL, f, F, gptr<const double>(nullptr),
-                                   gptr<double>(nullptr), 0.0);
+  op_apply<double, NZ>(cold, A, FIN_FULL, f, F, gptr<const double>(nullptr),
+                       gptr<double>(nullptr), 0.0);
   for (int e = tid(); e < n; e += nthr()) {
     const int j = e / nx, i = e - j * nx;
     const double sx = g.ao[i] + g.bo[i] * sig[j];
@@ -217,9 +214,8 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_rhs(const TankDesc* __rest
   col_dsig<double, NZ>(nx, A.Ds, us, t1);
   col_dsig<double, NZ>(nx, A.Ds, wsv, t3);
   __syncthreads();
-  dx_rows<double, kStageFs16>(NZ, nx, c.log2nx, c.kfac, fftb,
-                             [=](int j, int i) { return us[j * nx + i]; },
-                             [=](int j, int i, double v) { t2[j * nx + i] = v; });
+  dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb, [=](int j, int i) { return us[j * nx + i]; },
+                  [=](int j, int i, double v) { t2[j * nx + i] = v; });
   const double scale = cf.rho / (cf.b * cf.dt);
   for (int e = tid(); e < n; e += nthr()) {
     const int j = e / nx, i = e - j * nx;
@@ -263,9 +259,8 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_update(const TankDesc* __r
   col_dsig<double, NZ>(nx, A.Ds, pp, ts);
   __syncthreads();
   if (comp == 0)
-    dx_rows<double, kStageFs16>(NZ, nx, c.log2nx, c.kfac, fftb,
-                               [=](int j, int i) { return pp[j * nx + i]; },
-                               [=](int j, int i, double v) { t2[j * nx + i] = v; });
+    dx_rows<double>(NZ, nx, c.log2nx, c.kfac, fftb, [=](int j, int i) { return pp[j * nx + i]; },
+                    [=](int j, int i, double v) { t2[j * nx + i] = v; });
   const double ir = 1.0 / cf.rho;
   for (int e = tid(); e < n; e += nthr()) {
     const int j = e / nx, i = e - j * nx;
@@ -277,10 +272,9 @@ __global__ void __launch_bounds__(kStageThreads) k_rk_update(const TankDesc* __r
     r[e] = q[e] + cf.b * a;
   }
   __syncthreads();
-  spectral_rows<double, kStageFs16>(NZ, nx, td.log2nx, fftb,
-                                    [=](int j, int i) { return r[j * nx + i]; },
-                                    [=](int k, cpx<double> v) { return filt_mul(fx, nx, k, v); },
-                                    [=](int j, int i, double v) { tf[j * nx + i] = v; });
+  spectral_rows<double>(NZ, nx, td.log2nx, fftb, [=](int j, int i) { return r[j * nx + i]; },
+                        [=](int k, cpx<double> v) { return filt_mul(fx, nx, k, v); },
+                        [=](int j, int i, double v) { tf[j * nx + i] = v; });
   col_dsig<double, NZ>(nx, fz, tf, q);
   if (cf.noslip) {
     __syncthreads();
