@@ -260,9 +260,10 @@ int pmgw_stream_target(pmgw_plan plan, const double* coef, int32_t nmodes, doubl
 int pmgw_relax(pmgw_plan plan, const double* r, const double* u_t, const double* w_t,
                const double* eta_t, double* u, double* w, double* eta);
 
-/* Forget the pressures recorded for opts.guess_steps (e.g. before stepping a new initial state
- * with the same plan); the next rk4_stage calls start from p as passed until two steps are
- * recorded again. No-op for plans without guess_steps. */
+/* Forget the pressures recorded for opts.guess_steps and the last extrapolation kept for
+ * opts.guess_correct (e.g. before stepping a new initial state with the same plan); the next
+ * rk4_stage calls start from p as passed until two steps are recorded again. No-op for plans
+ * without guess_steps. */
 int pmgw_history_reset(pmgw_plan plan);
 
 /*

@@ -418,7 +418,8 @@ def relax(plan, r, u_t, w_t, eta_t, u, w, eta):
 
 
 def history_reset(plan):
-    """Forget the stage pressures recorded for opts.guess_steps."""
+    """Forget the stage pressures recorded for opts.guess_steps (and the last extrapolation of
+    opts.guess_correct)."""
     _check(lib().pmgw_history_reset(plan._h))
 
 
